@@ -1,0 +1,127 @@
+"""CPU oracle for greedy binary code construction (TEST INFRASTRUCTURE ONLY).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It wraps ``greedy_oracle.c`` (plain C,
+built with gcc) through ctypes and shares nothing with the HIP library.
+
+Functions follow Paliwal et al., arXiv:1507.05398:
+  * ``greedy_scan``   -- the greedy algorithm as defined in section "Greedy
+    Algorithms and Different Orderings": candidates in order, each compared
+    with every accepted word (newest first, stop at the first word closer than
+    d), appended when none is closer than d.  Reports the checks performed
+    (``w_ee``) and the exhaustive count (``w_full``).
+  * ``greedy_ball``   -- the same output by ball marking (rejected exactly when
+    within d-1 of an earlier accepted word); reports the same ``w_ee``.
+  * ``order_table``   -- the four orderings of section "Ordering
+    Implementation" (readings in ``greedy_oracle.c``).
+  * ``verify_certificate`` -- independent characterisation of the output.
+  * ``distance`` -- Hamming distance, section "Hamming Distance".
+
+Parity: the GREVLEX tie-break is "parity unpinned" beyond the textbook
+definition; everything else is pinned by the CPU tests.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+LEX, GRAY, GRLEX, GREVLEX = 0, 1, 2, 3
+ORDERINGS = {"lex": LEX, "gray": GRAY, "grlex": GRLEX, "grevlex": GREVLEX}
+
+OK, EINVAL, ECAPACITY, ENOMEM, EFAIL = 0, -1, -2, -4, -5
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = _build.LIBRARY
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SOURCE):
+        _build.build()
+    lib = ctypes.CDLL(path)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.gco_distance.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+    lib.gco_distance.restype = ctypes.c_uint
+    lib.gco_weight.argtypes = [ctypes.c_uint32]
+    lib.gco_weight.restype = ctypes.c_uint
+    lib.gco_order_table.argtypes = [ctypes.c_int, ctypes.c_int, u32p]
+    lib.gco_order_table.restype = ctypes.c_int
+    lib.gco_greedy_scan.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, u32p,
+                                    ctypes.c_uint64, u64p, u64p, u64p]
+    lib.gco_greedy_scan.restype = ctypes.c_int
+    lib.gco_greedy_ball.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, u32p,
+                                    ctypes.c_uint64, u64p, u64p]
+    lib.gco_greedy_ball.restype = ctypes.c_int
+    lib.gco_verify_certificate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, u32p,
+                                           ctypes.c_uint64]
+    lib.gco_verify_certificate.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _u32(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+class OracleError(RuntimeError):
+    def __init__(self, rc, what):
+        super().__init__(f"{what} failed with code {rc}")
+        self.rc = rc
+
+
+def distance(a: int, b: int) -> int:
+    """Hamming distance: popcount(a XOR b)."""
+    return int(_load().gco_distance(a, b))
+
+
+def order_table(n: int, ordering: int) -> np.ndarray:
+    """All 2^n words of F_2^n in the given ordering (n <= 28)."""
+    out = np.zeros(1 << n, dtype=np.uint32)
+    rc = _load().gco_order_table(n, ordering, _u32(out))
+    if rc:
+        raise OracleError(rc, "order_table")
+    return out
+
+
+def _bound(n: int) -> int:
+    # Worst case: d = 1 keeps every vector.
+    return 1 << n
+
+
+def greedy_scan(n: int, d: int, ordering: int, cap: int = None):
+    """Plain-scan greedy.  Returns (words uint32[|C|], w_ee, w_full)."""
+    cap = _bound(n) if cap is None else cap
+    out = np.zeros(max(cap, 1), dtype=np.uint32)
+    count, ee, full = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    rc = _load().gco_greedy_scan(n, d, ordering, _u32(out), cap, ctypes.byref(count),
+                                 ctypes.byref(ee), ctypes.byref(full))
+    if rc:
+        raise OracleError(rc, "greedy_scan")
+    return out[: count.value].copy(), ee.value, full.value
+
+
+def greedy_ball(n: int, d: int, ordering: int, cap: int = None, want_w_ee: bool = False):
+    """Ball-marking greedy.  Returns (words, w_ee or None)."""
+    cap = _bound(n) if cap is None else cap
+    out = np.zeros(max(cap, 1), dtype=np.uint32)
+    count, ee = ctypes.c_uint64(), ctypes.c_uint64()
+    rc = _load().gco_greedy_ball(n, d, ordering, _u32(out), cap, ctypes.byref(count),
+                                 ctypes.byref(ee) if want_w_ee else None)
+    if rc:
+        raise OracleError(rc, "greedy_ball")
+    return out[: count.value].copy(), (ee.value if want_w_ee else None)
+
+
+def verify_certificate(n: int, d: int, ordering: int, words) -> int:
+    """0 if ``words`` is the greedy code for (n, d, ordering), else 1/2/3 =
+    order / distance / maximality rule failed (n <= 20, brute force)."""
+    w = np.ascontiguousarray(words, dtype=np.uint32)
+    if w.size == 0:
+        w = np.zeros(1, dtype=np.uint32)
+        return int(_load().gco_verify_certificate(n, d, ordering, _u32(w), 0))
+    return int(_load().gco_verify_certificate(n, d, ordering, _u32(w), w.size))

@@ -1,0 +1,359 @@
+/*
+ * greedy_oracle.c -- plain CPU oracle for greedy binary code construction.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path links, loads or
+ * calls this file: only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg do.  It shares no code, header, table or constant with the
+ * HIP library; the two are compared output against output.
+ *
+ * What it computes (Paliwal, Tiwary, Chaudhury, Gupta, "Generating Binary
+ * Optimal Codes Using Heterogeneous Parallel Computing", arXiv:1507.05398):
+ *
+ *   Section "Greedy Algorithms and Different Orderings": order all 2^n vectors
+ *   of F_2^n, start from the zero vector, and append each vector in turn to
+ *   the code C if its Hamming distance to every codeword already in C is at
+ *   least d.  Stop when all 2^n vectors have been examined.
+ *
+ *   Section "Hamming Distance": the distance of two words is the number of
+ *   coordinates where they differ = popcount(a XOR b).
+ *
+ *   Section "Ordering Implementation": four orderings -- lexicographic, Gray,
+ *   graded-lexicographic and graded-reverse-lexicographic.  The paper names
+ *   but does not define the last three; the readings used here are:
+ *     LEX      vectors as binary numbers, increasing from 0 (the listing of
+ *              Example 1: 000, 001, 010, ..., 111).
+ *     GRAY     the binary-reflected Gray code, built by reflection.
+ *     GRLEX    weight ascending; inside one weight, the lexicographic order
+ *              (leftmost coordinate most significant), i.e. increasing value.
+ *     GREVLEX  weight ascending; inside one weight, the graded reverse
+ *              lexicographic monomial order of Cox, Little and O'Shea
+ *              (exponent vectors alpha, beta of equal weight: alpha > beta iff
+ *              the rightmost non-zero entry of alpha - beta is negative),
+ *              listed from smallest to largest.
+ *   Bit convention: coordinate x_1 (leftmost character of the paper's
+ *   strings) is bit n-1 of the word, x_n is bit 0.
+ *
+ * Two exact algorithms are provided:
+ *   gco_greedy_scan  -- the definition itself: for every position, compare the
+ *                       candidate with the accepted words, newest first, and
+ *                       stop at the first word closer than d.  It also counts
+ *                       the distance checks it performs (W_ee) and the checks
+ *                       an exhaustive scan would perform (W_full).
+ *   gco_greedy_ball  -- ball marking: a vector is rejected exactly when it lies
+ *                       within distance d-1 of an earlier accepted word, so on
+ *                       acceptance every vector of the radius-(d-1) ball is
+ *                       marked.  Same output; used where the scan is too slow.
+ *
+ * Parity status: every function here is pinned by the CPU tests against the
+ * paper's worked example (Example 1), closed forms (Hamming, extended Hamming
+ * and Golay lexicodes, degenerate d), invariants (linearity of LEX/GRAY
+ * lexicodes, LEX = GRLEX as sets for d a power of two), an independent
+ * certificate check, and brute force on tiny n -- except the GREVLEX
+ * within-weight tie-break, for which the paper prints no example or property:
+ * parity unpinned beyond the textbook definition (checked against the n=4
+ * listing written out by hand in the tests).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define GCO_LEX 0
+#define GCO_GRAY 1
+#define GCO_GRLEX 2
+#define GCO_GREVLEX 3
+
+#define GCO_OK 0
+#define GCO_EINVAL (-1)
+#define GCO_ECAPACITY (-2)
+#define GCO_ENOMEM (-4)
+#define GCO_EFAIL (-5)
+
+/* Largest n for which an ordering table of 2^n words is materialised. */
+#define GCO_TABLE_MAX_N 28
+
+/* ------------------------------------------------------------------ */
+/* Hamming distance and weight (section "Hamming Distance")           */
+/* ------------------------------------------------------------------ */
+
+/* Number of coordinates in which a and b differ: XOR, then count ones. */
+unsigned gco_distance(uint32_t a, uint32_t b)
+{
+    return (unsigned)__builtin_popcount(a ^ b);
+}
+
+/* Number of non-zero coordinates (the weight of a word). */
+unsigned gco_weight(uint32_t x)
+{
+    return (unsigned)__builtin_popcount(x);
+}
+
+/* ------------------------------------------------------------------ */
+/* Orderings of F_2^n (section "Ordering Implementation")             */
+/* ------------------------------------------------------------------ */
+
+/* Binary-reflected Gray code, from its recursive definition: the list for
+ * k coordinates is the list for k-1 coordinates with a leading 0, followed by
+ * the same list reversed with a leading 1.  Returns the word at position p. */
+static uint32_t gray_reflected(uint64_t p, int k)
+{
+    uint32_t word = 0;
+    while (k > 0) {
+        uint64_t half = 1ull << (k - 1);
+        if (p >= half) {               /* second half: leading 1, reversed */
+            word |= (uint32_t)half;
+            p = (half - 1) - (p - half);
+        }
+        --k;
+    }
+    return word;
+}
+
+/* Cox-Little-O'Shea graded reverse lexicographic comparison of two words of
+ * equal weight, read as exponent vectors (x_1 .. x_n) with x_1 = bit n-1.
+ * alpha > beta iff the rightmost non-zero entry of alpha - beta is negative.
+ * "Rightmost" coordinate x_n is bit 0, so walk from bit 0 upwards. */
+static int grevlex_greater(uint32_t alpha, uint32_t beta, int n)
+{
+    for (int bit = 0; bit < n; ++bit) {
+        int a = (alpha >> bit) & 1, b = (beta >> bit) & 1;
+        if (a != b)
+            return (a - b) < 0; /* entry of alpha - beta is a - b */
+    }
+    return 0; /* equal */
+}
+
+static int g_sort_n; /* qsort has no context argument in plain C */
+
+static int cmp_grevlex_ascending(const void *pa, const void *pb)
+{
+    uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
+    if (grevlex_greater(a, b, g_sort_n)) return 1;
+    if (grevlex_greater(b, a, g_sort_n)) return -1;
+    return 0;
+}
+
+/* Fill table[0 .. 2^n) with the ordering, straight from its definition.
+ * Graded orders go through the space once per weight, collecting the words of
+ * that weight, then order that class by the chosen tie-break. */
+int gco_order_table(int n, int ordering, uint32_t *table)
+{
+    if (n < 1 || n > GCO_TABLE_MAX_N || !table) return GCO_EINVAL;
+    uint64_t size = 1ull << n;
+    switch (ordering) {
+    case GCO_LEX:
+        for (uint64_t p = 0; p < size; ++p) table[p] = (uint32_t)p;
+        return GCO_OK;
+    case GCO_GRAY:
+        for (uint64_t p = 0; p < size; ++p) table[p] = gray_reflected(p, n);
+        return GCO_OK;
+    case GCO_GRLEX:
+    case GCO_GREVLEX: {
+        uint64_t at = 0;
+        for (int w = 0; w <= n; ++w) {
+            uint64_t start = at;
+            for (uint64_t x = 0; x < size; ++x)      /* increasing value */
+                if (gco_weight((uint32_t)x) == (unsigned)w) table[at++] = (uint32_t)x;
+            if (ordering == GCO_GREVLEX) {
+                g_sort_n = n;
+                qsort(table + start, at - start, sizeof(uint32_t), cmp_grevlex_ascending);
+            }
+        }
+        return at == size ? GCO_OK : GCO_EFAIL;
+    }
+    default:
+        return GCO_EINVAL;
+    }
+}
+
+/* Word at position p without a table, for the two orderings whose definition
+ * is positional. */
+static int positional(int ordering) { return ordering == GCO_LEX || ordering == GCO_GRAY; }
+
+static uint32_t position_word(int n, int ordering, uint64_t p)
+{
+    return ordering == GCO_LEX ? (uint32_t)p : gray_reflected(p, n);
+}
+
+/* Position -> word via the table when n allows, else positionally. */
+typedef struct {
+    int n, ordering;
+    uint32_t *table; /* NULL when positional */
+} order_t;
+
+static int order_open(order_t *o, int n, int ordering)
+{
+    o->n = n; o->ordering = ordering; o->table = NULL;
+    if (ordering < GCO_LEX || ordering > GCO_GREVLEX) return GCO_EINVAL;
+    if (positional(ordering)) return GCO_OK;
+    if (n <= GCO_TABLE_MAX_N) {
+        o->table = (uint32_t *)malloc(sizeof(uint32_t) << n);
+        if (!o->table) return GCO_ENOMEM;
+        int rc = gco_order_table(n, ordering, o->table);
+        if (rc) { free(o->table); o->table = NULL; return rc; }
+        return GCO_OK;
+    }
+    return GCO_EINVAL; /* graded orders need a table */
+}
+
+static inline uint32_t order_at(const order_t *o, uint64_t p)
+{
+    return o->table ? o->table[p] : position_word(o->n, o->ordering, p);
+}
+
+static void order_close(order_t *o) { free(o->table); o->table = NULL; }
+
+/* ------------------------------------------------------------------ */
+/* The greedy algorithm, by definition (section "Greedy Algorithms ...") */
+/* ------------------------------------------------------------------ */
+
+static int check_args(int n, int d, int ordering, const uint64_t *count)
+{
+    if (n < 1 || n > 32 || d < 1 || ordering < GCO_LEX || ordering > GCO_GREVLEX || !count)
+        return GCO_EINVAL;
+    return GCO_OK;
+}
+
+/* Plain scan.  out has room for cap words; on success *count holds |C| and
+ * out[0 .. |C|) the codewords in acceptance order.  w_ee (may be NULL)
+ * receives the number of distance checks performed when each candidate is
+ * compared with the accepted words newest first and stops at the first word
+ * closer than d; w_full (may be NULL) receives sum over candidates of |C| at
+ * that moment (every candidate compared with every accepted word).
+ * Returns GCO_ECAPACITY if more than cap words would be accepted. */
+int gco_greedy_scan(int n, int d, int ordering, uint32_t *out, uint64_t cap,
+                    uint64_t *count, uint64_t *w_ee, uint64_t *w_full)
+{
+    int rc = check_args(n, d, ordering, count);
+    if (rc) return rc;
+    if (!out && cap) return GCO_EINVAL;
+    order_t o;
+    if ((rc = order_open(&o, n, ordering))) return rc;
+
+    uint64_t m = 0, ee = 0, full = 0, size = 1ull << n;
+    for (uint64_t p = 0; p < size; ++p) {
+        uint32_t x = order_at(&o, p);
+        int accept = 1;
+        for (uint64_t i = m; i-- > 0;) {            /* newest accepted word first */
+            ++ee;
+            if (gco_distance(x, out[i]) < (unsigned)d) { accept = 0; break; }
+        }
+        full += m;
+        if (accept) {
+            if (m == cap) { order_close(&o); *count = m; return GCO_ECAPACITY; }
+            out[m++] = x;
+        }
+    }
+    order_close(&o);
+    *count = m;
+    if (w_ee) *w_ee = ee;
+    if (w_full) *w_full = full;
+    return GCO_OK;
+}
+
+/* Visit every word within distance r of x (all sets of at most r coordinates
+ * flipped), marking it covered and, when last is given, recording that the
+ * newest accepted word covering it is number idx. */
+static void mark_ball(uint32_t x, int n, int r, uint8_t *covered, uint32_t *last, uint32_t idx)
+{
+    int pos[33];
+    /* flip-set of size k, as strictly increasing coordinate lists */
+    for (int k = 0; k <= r && k <= n; ++k) {
+        for (int i = 0; i < k; ++i) pos[i] = i;
+        for (;;) {
+            uint32_t y = x;
+            for (int i = 0; i < k; ++i) y ^= 1u << pos[i];
+            covered[y >> 3] |= (uint8_t)(1u << (y & 7));
+            if (last) last[y] = idx;
+            /* next combination of k out of n */
+            int i = k - 1;
+            while (i >= 0 && pos[i] == n - k + i) --i;
+            if (i < 0) break;
+            ++pos[i];
+            for (int j = i + 1; j < k; ++j) pos[j] = pos[j - 1] + 1;
+        }
+    }
+}
+
+/* Ball marking: same output as the plain scan.  w_ee (may be NULL) receives
+ * the same newest-first check count the plain scan would report: for a
+ * rejected candidate that is |C| minus the index of the newest accepted word
+ * within d-1, for an accepted one it is |C|.  Needs 2^n/8 bytes, plus 4*2^n
+ * bytes when w_ee is requested; n <= GCO_TABLE_MAX_N. */
+int gco_greedy_ball(int n, int d, int ordering, uint32_t *out, uint64_t cap,
+                    uint64_t *count, uint64_t *w_ee)
+{
+    int rc = check_args(n, d, ordering, count);
+    if (rc) return rc;
+    if (n > GCO_TABLE_MAX_N || (!out && cap)) return GCO_EINVAL;
+    order_t o;
+    if ((rc = order_open(&o, n, ordering))) return rc;
+    uint64_t size = 1ull << n;
+    uint8_t *covered = (uint8_t *)calloc(size / 8 + 1, 1);
+    uint32_t *last = w_ee ? (uint32_t *)malloc(sizeof(uint32_t) * size) : NULL;
+    if (!covered || (w_ee && !last)) {
+        free(covered); free(last); order_close(&o);
+        return GCO_ENOMEM;
+    }
+    uint64_t m = 0, ee = 0;
+    int r = d - 1;
+    for (uint64_t p = 0; p < size; ++p) {
+        uint32_t x = order_at(&o, p);
+        if (covered[x >> 3] & (1u << (x & 7))) {
+            if (last) ee += m - last[x];
+            continue;
+        }
+        if (m == cap) { rc = GCO_ECAPACITY; break; }
+        ee += m;
+        out[m] = x;
+        mark_ball(x, n, r, covered, last, (uint32_t)m);
+        ++m;
+    }
+    free(covered); free(last); order_close(&o);
+    *count = m;
+    if (rc) return rc;
+    if (w_ee) *w_ee = ee;
+    return GCO_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Certificate: an independent characterisation of the greedy output   */
+/* ------------------------------------------------------------------ */
+
+/* words[0 .. count) is the greedy code for (n, d, ordering) iff
+ *   (a) the words appear in strictly increasing position order,
+ *   (b) every two of them are at distance >= d, and
+ *   (c) every vector not in the list is within distance d-1 of a listed word
+ *       that comes earlier in the ordering.
+ * (By induction over positions: (b) says no listed word should have been
+ * rejected, (c) says every unlisted word was.)  Brute force; for small n.
+ * Returns 0 if the certificate holds, else 1 + the index of the failed rule. */
+int gco_verify_certificate(int n, int d, int ordering, const uint32_t *words, uint64_t count)
+{
+    if (n < 1 || n > 20 || d < 1 || !words) return GCO_EINVAL;
+    order_t o;
+    if (order_open(&o, n, ordering)) return GCO_EINVAL;
+    uint64_t size = 1ull << n;
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * size);
+    int8_t *member = (int8_t *)calloc(size, 1);
+    if (!pos || !member) { free(pos); free(member); order_close(&o); return GCO_ENOMEM; }
+    for (uint64_t p = 0; p < size; ++p) pos[order_at(&o, p)] = (int64_t)p;
+    int fail = 0;
+    for (uint64_t i = 0; i < count && !fail; ++i) {
+        if (words[i] >= size) fail = 1;
+        else if (i && pos[words[i]] <= pos[words[i - 1]]) fail = 1;
+        else member[words[i]] = 1;
+    }
+    for (uint64_t i = 0; i < count && !fail; ++i)
+        for (uint64_t j = i + 1; j < count; ++j)
+            if (gco_distance(words[i], words[j]) < (unsigned)d) { fail = 2; break; }
+    for (uint64_t y = 0; y < size && !fail; ++y) {
+        if (member[y]) continue;
+        int covered = 0;
+        for (uint64_t i = 0; i < count && !covered; ++i)
+            if (pos[words[i]] < pos[y] && gco_distance((uint32_t)y, words[i]) < (unsigned)d)
+                covered = 1;
+        if (!covered) fail = 3;
+    }
+    free(pos); free(member); order_close(&o);
+    return fail;
+}
