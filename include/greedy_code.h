@@ -1,0 +1,117 @@
+/*
+ * greedy_code.h -- C ABI of the MI355X (gfx950) greedy code construction
+ * library, libgreedy_code.so.
+ *
+ * The operation (Paliwal, Tiwary, Chaudhury, Gupta, "Generating Binary
+ * Optimal Codes Using Heterogeneous Parallel Computing", arXiv:1507.05398,
+ * section "Greedy Algorithms and Different Orderings"): order all 2^n vectors
+ * of F_2^n, start from the zero vector and append each vector in turn to the
+ * code C when its Hamming distance to every word already in C is at least d
+ * (section "Hamming Distance": distance = popcount(a XOR b)).  The result is
+ * the ordered list of accepted words; it is unique, and every entry point
+ * returns it bit for bit, in acceptance order.
+ *
+ * Words are uint32 bit masks: coordinate x_1 (the leftmost character of the
+ * paper's strings, e.g. "011") is bit n-1, x_n is bit 0.
+ *
+ * Orderings (section "Ordering Implementation"; the paper names them, the
+ * definitions are fixed here):
+ *   GC_LEX      position p holds the word with value p (Example 1's listing).
+ *   GC_GRAY     binary-reflected Gray code, p XOR (p >> 1).
+ *   GC_GRLEX    weight ascending; equal weights by increasing value.
+ *   GC_GREVLEX  weight ascending; equal weights by the graded reverse
+ *               lexicographic monomial order (Cox, Little, O'Shea): the word
+ *               with a 1 at the lowest differing bit comes first.
+ *
+ * Error codes: every entry point returns GC_OK (0) or a negative code; the
+ * thread-local message of the last failure is available from gc_last_error().
+ * No C++ exception crosses this boundary.
+ *
+ * Threading: calls may run concurrently from different threads on different
+ * streams; each call owns its device workspace.  A call does not return until
+ * its work on the given stream has finished (the result codes depend on it).
+ */
+#ifndef GREEDY_CODE_H
+#define GREEDY_CODE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { GC_LEX = 0, GC_GRAY = 1, GC_GRLEX = 2, GC_GREVLEX = 3 };
+
+enum {
+    GC_OK = 0,
+    GC_EINVAL = -1,    /* n outside [1,32], d < 1, unknown ordering, NULL pointer */
+    GC_ECAPACITY = -2, /* more words than the capacity given; the count is set to
+                          greedy_code_capacity(n, d) (host API) or the number of
+                          words that fit (device API) */
+    GC_EDEVICE = -3,   /* a HIP call failed; see gc_last_error() */
+    GC_ENOMEM = -4,    /* device or host allocation failed */
+    GC_ETIMEOUT = -5   /* a bounded device-side wait expired (no forward progress) */
+};
+
+/* Work counters of one call (optional output).  checks_* count executed
+ * distance checks (candidate x codeword pairs) by the kernel phase that ran
+ * them; they measure the device's total work, which includes speculation. */
+typedef struct gc_stats {
+    uint64_t count;           /* |C| */
+    uint64_t windows;         /* candidate windows processed */
+    uint64_t resolve_rounds;  /* deep-scan rounds over all windows */
+    uint64_t survivors;       /* window candidates that passed the near screen */
+    uint64_t checks_near;     /* near-screen checks executed */
+    uint64_t checks_deep;     /* deep-scan checks executed */
+    uint64_t checks_pairs;    /* in-window pair checks executed */
+    float kernel_ms;          /* device time of the construction kernel */
+} gc_stats;
+
+/* Tuning knobs (optional input; zero fields take the built-in defaults). */
+typedef struct gc_tuning {
+    uint64_t near_depth;    /* newest code words screened before the in-window
+                               resolve; 0 = default, UINT64_MAX = whole code */
+    uint32_t target_survivors; /* window survivors aimed for (<= 1024) */
+    uint32_t grid_blocks;   /* persistent workgroups; 0 = one per compute unit */
+} gc_tuning;
+
+/* Capacity (in words) that always suffices for (n, d): the sphere-packing
+ * bound 2^n / V(n, floor((d-1)/2)), using A(n, d) = A(n-1, d-1) for even d
+ * (every code of minimum distance d has at most this many words; the greedy
+ * code is one).  2^n for d <= 1, 1 for d > n.  Returns 0 for invalid n, d. */
+uint64_t greedy_code_capacity(int n, int d);
+
+/* Host-memory entry point.  out_words: caller-owned host array; *out_count on
+ * input is its capacity in words, on return the code size |C|.  The words
+ * are written in acceptance order.  Allocates and frees its own device memory
+ * and runs on the null stream.  GC_ECAPACITY: *out_count set to
+ * greedy_code_capacity(n, d), out_words contents unspecified. */
+int greedy_code(int n, int d, int ordering, uint32_t *out_words, uint64_t *out_count);
+
+/* Device-memory entry point: the words go to d_words (device array of
+ * `capacity` uint32, caller-owned, e.g. a torch tensor's data_ptr), the count
+ * to *d_count (one device uint64), both written on `hip_stream` (a
+ * hipStream_t, NULL = null stream).  The library allocates a temporary device
+ * workspace (about 2.5 MiB) stream-ordered and releases it before returning.
+ * GC_ECAPACITY: the first `capacity` words and *d_count = capacity. */
+int greedy_code_device(int n, int d, int ordering, uint32_t *d_words, uint64_t capacity,
+                       uint64_t *d_count, void *hip_stream);
+
+/* As greedy_code_device, with optional tuning (may be NULL) and work counters
+ * (may be NULL). */
+int greedy_code_device_ex(int n, int d, int ordering, uint32_t *d_words, uint64_t capacity,
+                          uint64_t *d_count, void *hip_stream, const gc_tuning *tuning,
+                          gc_stats *stats);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *gc_last_error(void);
+
+/* Library version string. */
+const char *gc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GREEDY_CODE_H */

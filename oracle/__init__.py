@@ -55,7 +55,7 @@ def _load():
                                     ctypes.c_uint64, u64p, u64p, u64p]
     lib.gco_greedy_scan.restype = ctypes.c_int
     lib.gco_greedy_ball.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, u32p,
-                                    ctypes.c_uint64, u64p, u64p]
+                                    ctypes.c_uint64, u64p, u64p, u64p]
     lib.gco_greedy_ball.restype = ctypes.c_int
     lib.gco_verify_certificate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, u32p,
                                            ctypes.c_uint64]
@@ -105,16 +105,21 @@ def greedy_scan(n: int, d: int, ordering: int, cap: int = None):
     return out[: count.value].copy(), ee.value, full.value
 
 
-def greedy_ball(n: int, d: int, ordering: int, cap: int = None, want_w_ee: bool = False):
-    """Ball-marking greedy.  Returns (words, w_ee or None)."""
+def greedy_ball(n: int, d: int, ordering: int, cap: int = None, want_w_ee: bool = False,
+                want_w_full: bool = False):
+    """Ball-marking greedy.  Returns (words, w_ee or None), or
+    (words, w_ee or None, w_full) when want_w_full."""
     cap = _bound(n) if cap is None else cap
     out = np.zeros(max(cap, 1), dtype=np.uint32)
-    count, ee = ctypes.c_uint64(), ctypes.c_uint64()
+    count, ee, full = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
     rc = _load().gco_greedy_ball(n, d, ordering, _u32(out), cap, ctypes.byref(count),
-                                 ctypes.byref(ee) if want_w_ee else None)
+                                 ctypes.byref(ee) if want_w_ee else None, ctypes.byref(full))
     if rc:
         raise OracleError(rc, "greedy_ball")
-    return out[: count.value].copy(), (ee.value if want_w_ee else None)
+    words = out[: count.value].copy()
+    if want_w_full:
+        return words, (ee.value if want_w_ee else None), full.value
+    return words, (ee.value if want_w_ee else None)
 
 
 def verify_certificate(n: int, d: int, ordering: int, words) -> int:

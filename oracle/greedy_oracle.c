@@ -277,10 +277,11 @@ static void mark_ball(uint32_t x, int n, int r, uint8_t *covered, uint32_t *last
 /* Ball marking: same output as the plain scan.  w_ee (may be NULL) receives
  * the same newest-first check count the plain scan would report: for a
  * rejected candidate that is |C| minus the index of the newest accepted word
- * within d-1, for an accepted one it is |C|.  Needs 2^n/8 bytes, plus 4*2^n
- * bytes when w_ee is requested; n <= GCO_TABLE_MAX_N. */
+ * within d-1, for an accepted one it is |C|.  w_full (may be NULL) receives
+ * the sum over candidates of |C| at that moment.  Needs 2^n/8 bytes, plus
+ * 4*2^n bytes when w_ee is requested; n <= GCO_TABLE_MAX_N. */
 int gco_greedy_ball(int n, int d, int ordering, uint32_t *out, uint64_t cap,
-                    uint64_t *count, uint64_t *w_ee)
+                    uint64_t *count, uint64_t *w_ee, uint64_t *w_full)
 {
     int rc = check_args(n, d, ordering, count);
     if (rc) return rc;
@@ -294,10 +295,11 @@ int gco_greedy_ball(int n, int d, int ordering, uint32_t *out, uint64_t cap,
         free(covered); free(last); order_close(&o);
         return GCO_ENOMEM;
     }
-    uint64_t m = 0, ee = 0;
+    uint64_t m = 0, ee = 0, full = 0;
     int r = d - 1;
     for (uint64_t p = 0; p < size; ++p) {
         uint32_t x = order_at(&o, p);
+        full += m;
         if (covered[x >> 3] & (1u << (x & 7))) {
             if (last) ee += m - last[x];
             continue;
@@ -312,6 +314,7 @@ int gco_greedy_ball(int n, int d, int ordering, uint32_t *out, uint64_t cap,
     *count = m;
     if (rc) return rc;
     if (w_ee) *w_ee = ee;
+    if (w_full) *w_full = full;
     return GCO_OK;
 }
 

@@ -1,0 +1,14 @@
+"""MI355X (gfx950) greedy binary code construction (arXiv:1507.05398).
+
+The computation lives in ``libgreedy_code.so`` (hand-written HIP, C ABI in
+``include/greedy_code.h``); this package only marshals arguments to it.
+"""
+from ._native import (EXPORTS, GC_ECAPACITY, GC_EDEVICE, GC_EINVAL, GC_ENOMEM, GC_ETIMEOUT,
+                      GC_GRAY, GC_GREVLEX, GC_GRLEX, GC_LEX, GC_OK, ORDERINGS, GreedyCodeError,
+                      device_code, gc_last_error, gc_version, greedy_code, greedy_code_capacity,
+                      greedy_code_device, greedy_code_device_ex, load)
+
+__all__ = ["EXPORTS", "GC_ECAPACITY", "GC_EDEVICE", "GC_EINVAL", "GC_ENOMEM", "GC_ETIMEOUT",
+           "GC_GRAY", "GC_GREVLEX", "GC_GRLEX", "GC_LEX", "GC_OK", "ORDERINGS", "GreedyCodeError",
+           "device_code", "gc_last_error", "gc_version", "greedy_code", "greedy_code_capacity",
+           "greedy_code_device", "greedy_code_device_ex", "load"]

@@ -1,0 +1,94 @@
+"""Write tests/golden/expected_codes.txt from the CPU oracle only.
+
+For every workload instance the file records |C|, the SHA-256 of the code
+(uint32 little-endian words in acceptance order), W_ee (distance checks of the
+newest-first sequential scan with early exit) and W_full (checks of the
+exhaustive scan).  Instances (n, d, ordering):
+
+  * n=15, d=3, lex (the [15,11] Hamming code);
+  * lex, gray, grlex, grevlex at n in {20, 22, 24} with d in {3,4,5,6,8},
+    plus n=23 with d=7;
+  * lex and gray at n in {26, 28} with d=3 and at n=32 with d in {8,10,12}.
+
+Usage: python tests/golden/make_expected.py [--jobs J] [--only PREFIX]
+(about an hour on 8 cores; the n=32 instances dominate).
+"""
+import argparse
+import hashlib
+import os
+import sys
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+
+OUT = os.path.join(HERE, "expected_codes.txt")
+NAMES = ["lex", "gray", "grlex", "grevlex"]
+
+
+def instances():
+    yield (15, 3, "lex")
+    for o in NAMES:
+        for n in (20, 22, 24):
+            for d in (3, 4, 5, 6, 8):
+                yield (n, d, o)
+        yield (23, 7, o)
+    for o in ("lex", "gray"):
+        for n in (26, 28):
+            yield (n, 3, o)
+        for d in (8, 10, 12):
+            yield (32, d, o)
+
+
+def solve(inst):
+    n, d, name = inst
+    t = time.time()
+    ordering = oracle.ORDERINGS[name]
+    if n <= 28 and d <= 6:
+        words, w_ee, w_full = oracle.greedy_ball(n, d, ordering, want_w_ee=True, want_w_full=True)
+        how = "ball"
+    else:
+        cap = 1 << 20
+        words, w_ee, w_full = oracle.greedy_scan(n, d, ordering, cap=cap)
+        how = "scan"
+    digest = hashlib.sha256(words.astype("<u4").tobytes()).hexdigest()
+    return inst, len(words), digest, w_ee, w_full, how, time.time() - t
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=4)
+    ap.add_argument("--only", default="")
+    args = ap.parse_args()
+    todo = [i for i in instances() if f"{i[0]}_{i[1]}_{i[2]}".startswith(args.only)]
+    old = {}
+    if os.path.exists(OUT):
+        for line in open(OUT):
+            if line.strip() and not line.startswith("#"):
+                old[line.split()[0]] = line.rstrip("\n")
+    # heaviest first
+    todo.sort(key=lambda i: (i[0] == 32, i[0], -i[1]), reverse=True)
+    with ProcessPoolExecutor(args.jobs) as ex:
+        for inst, m, digest, w_ee, w_full, how, dt in ex.map(solve, todo):
+            key = f"{inst[0]}_{inst[1]}_{inst[2]}"
+            old[key] = f"{key} {m} {digest} {w_ee} {w_full}"
+            print(f"{key}: |C|={m} w_ee={w_ee} w_full={w_full} ({how}, {dt:.1f}s)", flush=True)
+            write(old)
+
+
+def write(entries):
+    order = [f"{i[0]}_{i[1]}_{i[2]}" for i in instances()]
+    with open(OUT + ".tmp", "w") as f:
+        f.write("# Written by tests/golden/make_expected.py from the CPU oracle only.\n")
+        f.write("# key=n_d_ordering |C| sha256(uint32 LE words in acceptance order) W_ee W_full\n")
+        for k in order:
+            if k in entries:
+                f.write(entries[k] + "\n")
+    os.replace(OUT + ".tmp", OUT)
+
+
+if __name__ == "__main__":
+    main()

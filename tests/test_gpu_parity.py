@@ -1,0 +1,164 @@
+"""GPU parity: the HIP library against the CPU oracle, bit for bit.
+
+Every comparison is the exact ordered word list (the method is integer-only,
+so the tolerance is zero).  Small instances run the oracle live; the workload
+instances (n up to 32) compare against tests/golden/expected_codes.txt, which
+make_expected.py wrote from the oracle alone.
+"""
+import hashlib
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1507_05398_amd as gc
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+ORDS = ["lex", "gray", "grlex", "grevlex"]
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    gc.load()
+    return torch
+
+
+def gpu_code(n, d, o, **tuning):
+    log(f"[gpu] n={n} d={d} ord={o} tuning={tuning}")
+    words, stats = gc.device_code(n, d, o, **tuning)
+    return words.cpu().numpy().view(np.uint32).copy(), stats
+
+
+def oracle_code(n, d, o):
+    return oracle.greedy_ball(n, d, oracle.ORDERINGS[o])[0]
+
+
+def load_expected():
+    path = os.path.join(HERE, "golden", "expected_codes.txt")
+    out = {}
+    if os.path.exists(path):
+        for line in open(path):
+            if line.strip() and not line.startswith("#"):
+                key, m, digest, w_ee, w_full = line.split()
+                out[key] = (int(m), digest, int(w_ee), int(w_full))
+    return out
+
+
+EXPECTED = load_expected()
+
+
+def digest(words):
+    return hashlib.sha256(np.asarray(words, dtype="<u4").tobytes()).hexdigest()
+
+
+def test_worked_example_all_orderings():
+    assert gpu_code(3, 2, "lex")[0].tolist() == [0b000, 0b011, 0b101, 0b110]
+    for o in ORDS:
+        assert np.array_equal(gpu_code(3, 2, o)[0], oracle_code(3, 2, o))
+
+
+def test_hamming_15_3_lex():
+    words, stats = gpu_code(15, 3, "lex")
+    ref, w_ee, _ = oracle.greedy_scan(15, 3, oracle.LEX)
+    assert len(words) == 2048
+    assert np.array_equal(words, ref)
+    assert stats["count"] == 2048
+
+
+@pytest.mark.parametrize("o", ORDS)
+def test_all_small_parameters(o):
+    for n in range(1, 13):
+        for d in range(1, n + 2):
+            words, _ = gpu_code(n, d, o)
+            ref = oracle_code(n, d, o)
+            assert np.array_equal(words, ref), (n, d, o, len(words), len(ref))
+
+
+def test_host_entry_point():
+    for o in ORDS:
+        got = gc.greedy_code(14, 4, o)
+        assert np.array_equal(got, oracle_code(14, 4, o))
+
+
+@pytest.mark.parametrize("o", ORDS)
+@pytest.mark.parametrize("tuning", [dict(near_depth=1), dict(near_depth=64, target_survivors=16),
+                                    dict(near_depth=2 ** 63, target_survivors=1024),
+                                    dict(grid_blocks=1), dict(grid_blocks=7, near_depth=200)],
+                         ids=["near1", "near64_t16", "nearall_t1024", "grid1", "grid7"])
+def test_tuning_does_not_change_the_code(o, tuning):
+    for n, d in [(16, 3), (17, 4), (16, 5), (18, 6)]:
+        words, _ = gpu_code(n, d, o, **tuning)
+        assert np.array_equal(words, oracle_code(n, d, o)), (n, d, o, tuning)
+
+
+def test_capacity_error_keeps_prefix():
+    import torch
+    ref = oracle_code(16, 3, "lex")
+    cap = 1000
+    words = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    with pytest.raises(gc.GreedyCodeError) as e:
+        gc.greedy_code_device(16, 3, "lex", words, count)
+    assert e.value.rc == gc.GC_ECAPACITY
+    assert int(count.item()) == cap
+    assert np.array_equal(words.cpu().numpy().view(np.uint32), ref[:cap])
+
+
+def test_barrier_timeout_is_reported_not_hung():
+    # A zero spin limit makes every barrier wait expire at once: the kernel must
+    # still exit and the call must report GC_ETIMEOUT.
+    os.environ["GC_SPIN_LIMIT"] = "0"
+    try:
+        with pytest.raises(gc.GreedyCodeError) as e:
+            gc.device_code(16, 3, "lex", grid_blocks=8)
+        assert e.value.rc == gc.GC_ETIMEOUT
+    finally:
+        del os.environ["GC_SPIN_LIMIT"]
+    # and the library keeps working afterwards
+    words, _ = gpu_code(12, 3, "gray")
+    assert np.array_equal(words, oracle_code(12, 3, "gray"))
+
+
+def test_repeat_runs_are_identical():
+    a, _ = gpu_code(20, 4, "grlex")
+    for _ in range(2):
+        b, _ = gpu_code(20, 4, "grlex")
+        assert np.array_equal(a, b)
+
+
+def workload_keys(max_n):
+    keys = [k for k in EXPECTED if int(k.split("_")[0]) <= max_n]
+    return sorted(keys, key=lambda k: (int(k.split("_")[0]), k))
+
+
+@pytest.mark.parametrize("key", workload_keys(24))
+def test_workload_instances_up_to_24(key):
+    n, d, o = key.split("_")
+    m, dig, _, _ = EXPECTED[key]
+    t = time.time()
+    words, stats = gpu_code(int(n), int(d), o)
+    log(f"[gpu] {key}: |C|={len(words)} {time.time() - t:.2f}s rounds={stats['resolve_rounds']}")
+    assert len(words) == m
+    assert digest(words) == dig
+
+
+@pytest.mark.parametrize("key", [k for k in workload_keys(32) if int(k.split("_")[0]) > 24])
+def test_workload_instances_large(key):
+    n, d, o = key.split("_")
+    m, dig, _, _ = EXPECTED[key]
+    t = time.time()
+    words, stats = gpu_code(int(n), int(d), o)
+    log(f"[gpu] {key}: |C|={len(words)} {time.time() - t:.2f}s")
+    assert len(words) == m
+    assert digest(words) == dig

@@ -348,7 +348,7 @@ def test_work_counters_brute_force(n, d, ordering):
 @pytest.mark.parametrize("ordering", ORDS)
 @pytest.mark.parametrize("n,d", [(10, 2), (12, 3), (13, 4), (14, 5), (15, 3), (16, 6), (16, 3)])
 def test_plain_scan_equals_ball_marking(n, d, ordering):
-    words, w_ee, _ = oracle.greedy_scan(n, d, ordering)
-    words2, w_ee2 = oracle.greedy_ball(n, d, ordering, want_w_ee=True)
+    words, w_ee, w_full = oracle.greedy_scan(n, d, ordering)
+    words2, w_ee2, w_full2 = oracle.greedy_ball(n, d, ordering, want_w_ee=True, want_w_full=True)
     assert np.array_equal(words, words2)
-    assert w_ee == w_ee2
+    assert (w_ee, w_full) == (w_ee2, w_full2)
