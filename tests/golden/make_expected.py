@@ -69,8 +69,8 @@ def main():
         for line in open(OUT):
             if line.strip() and not line.startswith("#"):
                 old[line.split()[0]] = line.rstrip("\n")
-    # heaviest first
-    todo.sort(key=lambda i: (i[0] == 32, i[0], -i[1]), reverse=True)
+    # workload sweep first (fast), then the n=26/28 screens, then n=32
+    todo.sort(key=lambda i: (i[0] == 32, i[0] > 24, -i[0], i[1]))
     with ProcessPoolExecutor(args.jobs) as ex:
         for inst, m, digest, w_ee, w_full, how, dt in ex.map(solve, todo):
             key = f"{inst[0]}_{inst[1]}_{inst[2]}"
