@@ -74,6 +74,10 @@ typedef struct gc_tuning {
                                resolve; 0 = default, UINT64_MAX = whole code */
     uint32_t target_survivors; /* window survivors aimed for (<= 1024) */
     uint32_t grid_blocks;   /* persistent workgroups; 0 = one per compute unit */
+    uint32_t resolve_mode;  /* 0 = by ordering, 1 = tentative (deep-scan only the
+                               tentatively accepted survivors, repeat until
+                               stable), 2 = deep-scan every survivor once */
+    uint32_t reserved;      /* must be 0 */
 } gc_tuning;
 
 /* Capacity (in words) that always suffices for (n, d): the sphere-packing

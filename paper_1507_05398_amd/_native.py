@@ -40,7 +40,8 @@ class GcStats(ctypes.Structure):
 
 class GcTuning(ctypes.Structure):
     _fields_ = [("near_depth", ctypes.c_uint64), ("target_survivors", ctypes.c_uint32),
-                ("grid_blocks", ctypes.c_uint32)]
+                ("grid_blocks", ctypes.c_uint32), ("resolve_mode", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 _lib = None
@@ -125,9 +126,9 @@ def greedy_code_device(n: int, d: int, ordering, words, count, stream=None) -> N
 
 
 def greedy_code_device_ex(n: int, d: int, ordering, words, count, stream=None, near_depth=0,
-                          target_survivors=0, grid_blocks=0) -> dict:
+                          target_survivors=0, grid_blocks=0, resolve_mode=0) -> dict:
     """As greedy_code_device, with tuning knobs; returns the work counters."""
-    tuning = GcTuning(near_depth, target_survivors, grid_blocks)
+    tuning = GcTuning(near_depth, target_survivors, grid_blocks, resolve_mode, 0)
     stats = GcStats()
     rc = load().greedy_code_device_ex(n, d, _ordering(ordering), ctypes.c_void_p(words.data_ptr()),
                                       words.numel(), ctypes.c_void_p(count.data_ptr()),

@@ -60,8 +60,10 @@ namespace gcimpl {
 
 constexpr int kBlock = 1024;                          // threads per workgroup
 constexpr int kWaves = kBlock / 64;                   // waves per workgroup
-constexpr int kR = 4;                                 // candidates per lane in a screen item
-constexpr int kGroup = 64 * kR;                       // candidates per screen item
+constexpr int kTile = 256;                            // candidates per screen tile (4 rows of 64)
+constexpr int kRows = kTile / 64;
+constexpr int kSeg = 64 * kWaves;                     // code words per screen segment (64 per wave)
+constexpr int kMaxXcd = 16;
 constexpr int kSMax = 1024;                           // survivors per window (resolve capacity)
 constexpr int kNb = kSMax / 64;                       // survivor blocks of 64
 constexpr int kAdjWords = 64 * kNb * (kNb + 1) / 2;   // lower-triangular block adjacency
@@ -73,13 +75,23 @@ constexpr unsigned int kDefaultSpin = 1u << 25;
 
 enum : int { ST_UNKNOWN = 0, ST_PASS = 1, ST_FAIL = 2 };
 enum : int { ACT_NEXT = 0, ACT_DEEP = 1, ACT_STOP = 2 };
+enum : int { MODE_TENTATIVE = 1, MODE_DEEP_ALL = 2 };
+
+// Grid barrier state: one counter/generation pair per XCD (each on its own
+// 256-byte line) and one pair across XCD leaders.
+struct Bar {
+  unsigned int join_count;   // one-time membership count
+  unsigned int top_count;
+  unsigned int top_gen;
+  unsigned int pad0[61];
+  unsigned int xcd[kMaxXcd][64];   // [x][0] count, [x][1] generation, [x][2] members
+};
 
 struct Ctl {
   unsigned long long m;   // committed words
   unsigned long long p;   // start of the next window
   unsigned long long w;   // length of the next window
-  unsigned int bar_count;
-  unsigned int bar_gen;
+  unsigned int pad_bar[2];
   int status;
   int action;
   unsigned int ndeep;
@@ -88,11 +100,12 @@ struct Ctl {
 };
 
 struct Params {
-  int n, d, ord;
+  int n, d, ord, mode;
   unsigned long long total;   // 2^n
   uint32_t *code;
   unsigned long long capacity;
   Ctl *ctl;
+  Bar *bar;
   unsigned long long *count_out;
   uint32_t *win_dead;             // kWMax / 32 words
   unsigned long long *adj;        // kAdjWords
@@ -109,17 +122,36 @@ struct Tables {
   unsigned long long off[34];          // off[w] = number of words of weight < w
 };
 
+// Screen tile: candidate words and ids (double-buffered for compaction), code
+// segment (double-buffered), per-wave conflict masks.
+struct TileLds {
+  alignas(16) uint32_t seg[2][kSeg];
+  uint32_t cw[2][kTile];
+  uint32_t ci[2][kTile];
+  unsigned long long killw[kWaves][kRows];
+  unsigned int wcnt[kWaves];
+};
+
+// In-window resolve (workgroup 0 only).
+struct ResolveLds {
+  unsigned long long adj[kAdjWords];   // survivor adjacency (earlier-neighbour masks)
+  unsigned long long accm[kNb];        // accepted mask per block
+  uint32_t tlist[kSMax];               // tentatively accepted words
+};
+
 struct Lds {
   uint32_t s1w[kSMax];                 // window survivors, in position order
-  uint8_t st[kSMax];                   // deep status of each survivor (D only)
+  uint8_t st[kSMax];                   // deep status of each survivor (resolve only)
   Tables tab;
   unsigned long long p0, m0, w, pe, lo;
   unsigned int s, s_tot, ndeep, round, tcount, truncated;
   int status, action;
+  unsigned int xcd, xcd_members, nxcd;
   unsigned int wsum[kWaves];
-  unsigned long long adj[kAdjWords];   // D: survivor adjacency
-  unsigned long long accm[kNb];        // D: accepted mask per block
-  uint32_t tlist[kSMax];               // D: tentatively accepted words
+  union alignas(16) {
+    TileLds t;
+    ResolveLds r;
+  } u;
 };
 
 // ---------------------------------------------------------------------------
@@ -157,31 +189,83 @@ __device__ __forceinline__ void set_status(Ctl *ctl, int code) {
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid-wide barrier for a cooperative launch.  Every wave drains its memory
-// traffic, the workgroup meets, thread 0 arrives with release semantics and
-// waits (bounded) for the generation to move on, then acquires.  A wait that
-// exceeds spin_limit records GC_ETIMEOUT instead of hanging.
-__device__ void grid_barrier(Ctl *ctl, unsigned int spin_limit) {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
+__device__ __forceinline__ unsigned int xcc_id() {
+  unsigned int v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(v));
+  return v & (kMaxXcd - 1);
+}
+
+// Bounded spin until *p != old; records GC_ETIMEOUT and gives up after
+// spin_limit polls so that no wait can hang the device.
+__device__ __forceinline__ void wait_change(unsigned int *p, unsigned int old, Ctl *ctl,
+                                            unsigned int spin_limit) {
+  unsigned int spins = 0;
+  while (ld_relaxed(p) == old) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > spin_limit) {
+      set_status(ctl, GC_ETIMEOUT);
+      break;
+    }
+  }
+}
+
+// One-time registration: every workgroup counts itself on its XCD, then all
+// wait until the whole grid has registered, so that each XCD leader knows how
+// many workgroups to expect (no assumption about the block -> XCD mapping).
+__device__ void barrier_join(Lds &L, Bar *B, Ctl *ctl, unsigned int spin_limit) {
   if (threadIdx.x == 0) {
-    unsigned int gen = ld_relaxed(&ctl->bar_gen);
-    unsigned int arrived =
-        __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived + 1 == gridDim.x) {
-      __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&ctl->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      unsigned int spins = 0;
-      while (ld_relaxed(&ctl->bar_gen) == gen) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > spin_limit) {
-          set_status(ctl, GC_ETIMEOUT);
-          break;
-        }
+    const unsigned int x = xcc_id();
+    __hip_atomic_fetch_add(&B->xcd[x][2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&B->join_count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned int spins = 0;
+    while (ld_relaxed(&B->join_count) < gridDim.x) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > spin_limit) {
+        set_status(ctl, GC_ETIMEOUT);
+        break;
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    unsigned int nx = 0;
+    for (int i = 0; i < kMaxXcd; ++i) nx += ld_relaxed(&B->xcd[i][2]) > 0;
+    L.xcd = x;
+    L.xcd_members = ld_relaxed(&B->xcd[x][2]);
+    L.nxcd = nx;
+  }
+  __syncthreads();
+}
+
+// Grid-wide barrier for a cooperative launch, two levels.  Workgroups of one
+// XCD meet on that XCD's counter; the last to arrive (the XCD leader) makes
+// the XCD's writes visible device-wide (release), meets the other leaders,
+// acquires, and releases its XCD.  Every workgroup then acquires at agent
+// scope before reading data written elsewhere.  All waits are bounded.
+__device__ void grid_barrier(Lds &L, Bar *B, Ctl *ctl, unsigned int spin_limit) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int *xc = &B->xcd[L.xcd][0];
+    unsigned int *xg = &B->xcd[L.xcd][1];
+    const unsigned int g = ld_relaxed(xg);
+    const unsigned int a = __hip_atomic_fetch_add(xc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (a + 1 == L.xcd_members) {
+      __hip_atomic_store(xc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned int tg = ld_relaxed(&B->top_gen);
+      const unsigned int b =
+          __hip_atomic_fetch_add(&B->top_count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (b + 1 == L.nxcd) {
+        __hip_atomic_store(&B->top_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&B->top_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        wait_change(&B->top_gen, tg, ctl, spin_limit);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __builtin_amdgcn_s_waitcnt(0);
+      __hip_atomic_fetch_add(xg, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      wait_change(xg, g, ctl, spin_limit);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
     __builtin_amdgcn_s_waitcnt(0);
   }
   __syncthreads();
@@ -246,70 +330,165 @@ __device__ void init_tables(Tables &T, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// The screen: kR candidates per lane against code[a, b), newest first
+// The screen: a tile of candidates against code[a, b), whole workgroup
 // ---------------------------------------------------------------------------
 
-// Returns the bits k of `live` whose candidate x[k] is closer than d to some
-// word of code[a, b).  Stops as soon as every live candidate of the wave has a
-// conflict.  `*scanned` receives the number of code words visited.
-__device__ __forceinline__ uint32_t screen_range(const uint32_t *code, unsigned long long a,
-                                                 unsigned long long b, const uint32_t (&x)[kR],
-                                                 uint32_t live, uint32_t d,
-                                                 unsigned long long *scanned) {
-  uint32_t acc[kR];
-#pragma unroll
-  for (int k = 0; k < kR; ++k) acc[k] = (live >> k) & 1 ? 0xffffffffu : 0u;
-  unsigned long long visited = 0;
-  if (b > a) {
-    long long lo_blk = (long long)(a & ~15ull);
-    for (long long base = (long long)((b - 1) & ~15ull); base >= lo_blk; base -= 16) {
-      uint32_t c[16];
-      if ((unsigned long long)base >= a && (unsigned long long)base + 16 <= b) {
-        const uint4 *q = reinterpret_cast<const uint4 *>(code + base);
-        uint4 v0 = q[0], v1 = q[1], v2 = q[2], v3 = q[3];
-        c[0] = v0.x; c[1] = v0.y; c[2] = v0.z; c[3] = v0.w;
-        c[4] = v1.x; c[5] = v1.y; c[6] = v1.z; c[7] = v1.w;
-        c[8] = v2.x; c[9] = v2.y; c[10] = v2.z; c[11] = v2.w;
-        c[12] = v3.x; c[13] = v3.y; c[14] = v3.z; c[15] = v3.w;
-      } else {
-        // Edge block: clamp indices into [a, b); repeated words do not change
-        // a minimum distance.
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          long long idx = base + i;
-          idx = idx < (long long)a ? (long long)a : idx;
-          idx = idx > (long long)b - 1 ? (long long)b - 1 : idx;
-          c[i] = code[idx];
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < kR; ++k) {
-#pragma unroll
-        for (int i = 0; i < 16; i += 2) acc[k] = umin3(acc[k], dist(x[k], c[i]), dist(x[k], c[i + 1]));
-      }
-      visited += 16;
-      bool running = false;
-#pragma unroll
-      for (int k = 0; k < kR; ++k) running |= acc[k] >= d;
-      if (!__any(running)) break;
-    }
+// Candidates of a screen: window positions (id = offset from the window
+// start) or the deep list (id = index into deep_word).  `dead` holds one bit
+// per id; a set bit means "closer than d to a committed word".
+struct Source {
+  const Tables *tab;
+  int n, ord;
+  unsigned long long p0;
+  const uint32_t *words;  // deep list, or null for window positions
+  uint32_t *dead;
+  __device__ uint32_t word(uint32_t id) const {
+    return words ? words[id] : position_word(*tab, n, ord, p0 + id);
   }
-  *scanned += visited;
-  uint32_t conf = 0;
+  __device__ bool is_dead(uint32_t id) const { return (ld_relaxed(&dead[id >> 5]) >> (id & 31)) & 1; }
+  __device__ void kill(uint32_t id) const {
+    __hip_atomic_fetch_or(&dead[id >> 5], 1u << (id & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+
+// Workgroup compaction: threads of the first kRows waves offer (keep, word,
+// id); kept entries go densely and in order to buffer dst.  Returns the count.
+__device__ unsigned int tile_compact(TileLds &T, int dst, bool keep, uint32_t word, uint32_t id) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const unsigned long long m = ballot(keep);
+  if (lane == 0 && wave < kRows) T.wcnt[wave] = (unsigned int)__builtin_popcountll(m);
+  __syncthreads();
+  unsigned int base = 0, total = 0;
 #pragma unroll
-  for (int k = 0; k < kR; ++k)
-    if (((live >> k) & 1) && acc[k] < d) conf |= 1u << k;
-  return conf;
+  for (int w = 0; w < kRows; ++w) {
+    if (w < wave) base += T.wcnt[w];
+    total += T.wcnt[w];
+  }
+  if (keep) {
+    const unsigned int pos = base + (unsigned int)__builtin_popcountll(m & lanemask_lt());
+    T.cw[dst][pos] = word;
+    T.ci[dst][pos] = id;
+  }
+  __syncthreads();
+  return total;
 }
 
-// Chunk length for a 2-D screen over `len` code words and `groups` candidate
-// groups: aim for about two items per wave of the grid, at least 256 words.
-__device__ __forceinline__ unsigned long long chunk_len(unsigned long long len, unsigned long long groups,
-                                                        unsigned long long nwaves) {
-  unsigned long long want = (len * groups + 2 * nwaves - 1) / (2 * nwaves);
-  if (want < 256) want = 256;
-  want = (want + 63) & ~63ull;
-  return want;
+// One wave against its 64 words of the staged segment, ROWS rows of 64 live
+// candidates; m[r] gets the lanes of row r closer than d to one of the words.
+template <int ROWS>
+__device__ __forceinline__ void segment_rows(const TileLds &T, int cur, int buf, unsigned int live,
+                                             uint32_t d, unsigned long long (&m)[kRows]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x[ROWS], acc[ROWS];
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) {
+    const unsigned int idx = 64u * r + lane;
+    x[r] = idx < live ? T.cw[cur][idx] : 0u;
+    acc[r] = 0xffffffffu;
+  }
+  const uint4 *sp = reinterpret_cast<const uint4 *>(&T.seg[buf][64 * wave]);
+#pragma unroll 4
+  for (int i = 0; i < 16; ++i) {
+    const uint4 c = sp[i];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      acc[r] = umin3(acc[r], dist(x[r], c.x), dist(x[r], c.y));
+      acc[r] = umin3(acc[r], dist(x[r], c.z), dist(x[r], c.w));
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) m[r] = 0;
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) m[r] = ballot(acc[r] < d && 64u * r + lane < live);
+}
+
+// Screen candidates id0 .. id0+nc-1 of `src` (nc <= kTile) against
+// code[a, b), newest segment first, with the whole workgroup: each wave takes
+// 64 words of a 1024-word segment staged in LDS (the next segment is
+// prefetched into registers meanwhile).  After every segment the conflicts of
+// all waves are merged, killed candidates are marked in `src`, candidates
+// killed elsewhere are dropped, and the survivors are compacted, so the work
+// per segment follows the live count and the loop stops when none is left.
+// Returns the executed checks (candidate slots x words).
+__device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint32_t *code, uint32_t id0,
+                                          uint32_t nc, unsigned long long a, unsigned long long b,
+                                          uint32_t d) {
+  TileLds &T = L.u.t;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  bool keep = false;
+  uint32_t word = 0, id = 0;
+  if (tid < (int)nc) {
+    id = id0 + tid;
+    keep = !src.is_dead(id);
+    if (keep) word = src.word(id);
+  }
+  unsigned int live = tile_compact(T, 0, keep, word, id);
+  int cur = 0, buf = 0;
+  unsigned long long checks = 0;
+  unsigned long long hi = b;
+  uint32_t nxt = 0;
+  if (live > 0 && hi > a) {
+    const unsigned long long lo_s = hi > a + kSeg ? hi - kSeg : a;
+    const unsigned long long idx = lo_s + tid;
+    nxt = code[idx < hi ? idx : hi - 1];
+  }
+  while (live > 0 && hi > a) {
+    const unsigned long long lo_s = hi > a + kSeg ? hi - kSeg : a;
+    T.seg[buf][tid] = nxt;
+    __syncthreads();
+    if (lo_s > a) {  // prefetch the next (older) segment
+      const unsigned long long lo2 = lo_s > a + kSeg ? lo_s - kSeg : a;
+      const unsigned long long idx = lo2 + tid;
+      nxt = code[idx < lo_s ? idx : lo_s - 1];
+    }
+    unsigned long long m[kRows];
+    const unsigned int rows = (live + 63) / 64;
+    if (rows == 1) segment_rows<1>(T, cur, buf, live, d, m);
+    else if (rows == 2) segment_rows<2>(T, cur, buf, live, d, m);
+    else if (rows == 3) segment_rows<3>(T, cur, buf, live, d, m);
+    else segment_rows<4>(T, cur, buf, live, d, m);
+    if (lane == 0) {
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) T.killw[wave][r] = m[r];
+    }
+    checks += 64ull * rows * kSeg;
+    __syncthreads();
+    keep = false;
+    if (tid < (int)live) {
+      unsigned long long k = 0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) k |= T.killw[w][tid >> 6];
+      const bool killed = (k >> (tid & 63)) & 1;
+      word = T.cw[cur][tid];
+      id = T.ci[cur][tid];
+      if (killed) src.kill(id);
+      keep = !killed && !src.is_dead(id);
+    }
+    live = tile_compact(T, cur ^ 1, keep, word, id);
+    cur ^= 1;
+    buf ^= 1;
+    hi = lo_s;
+  }
+  return checks;
+}
+
+// Split of a 2-D screen (tiles x code range of `len` words) into items for
+// the grid: enough range parts to give every workgroup an item, each part a
+// whole number of segments.
+struct Split {
+  unsigned long long tiles, parts, plen;
+};
+
+__device__ __forceinline__ Split make_split(unsigned long long ncand, unsigned long long len) {
+  Split sp;
+  sp.tiles = (ncand + kTile - 1) / kTile;
+  unsigned long long parts = (gridDim.x + sp.tiles - 1) / sp.tiles;
+  const unsigned long long maxparts = (len + kSeg - 1) / kSeg;
+  if (parts > maxparts) parts = maxparts;
+  if (parts < 1) parts = 1;
+  sp.plen = ((len + parts - 1) / parts + kSeg - 1) / kSeg * kSeg;
+  sp.parts = (len + sp.plen - 1) / sp.plen;
+  return sp;
 }
 
 // ---------------------------------------------------------------------------
@@ -322,15 +501,32 @@ __device__ void resolve_window(const Params &P, Lds &L) {
   const int nb = (int)((s + 63) / 64);
   const int nadj = 64 * nb * (nb + 1) / 2;
 
+  ResolveLds &R = L.u.r;
   if (L.round == 0) {
-    for (int i = tid; i < nadj; i += kBlock) L.adj[i] = P.adj[i];
     for (unsigned int j = tid; j < s; j += kBlock) L.st[j] = L.lo == 0 ? ST_PASS : ST_UNKNOWN;
+    if (P.mode == MODE_DEEP_ALL && L.lo > 0 && s > 0) {
+      // Scan every survivor once; the resolve after that round has every fact.
+      for (unsigned int k = tid; k < s; k += kBlock) {
+        P.deep_word[k] = L.s1w[k];
+        P.deep_idx[k] = k;
+      }
+      for (unsigned int k = tid; k < (s + 31) / 32; k += kBlock) P.deep_fail[k] = 0;
+      if (tid == 0) {
+        L.ndeep = s;
+        P.ctl->ndeep = s;
+        P.ctl->action = ACT_DEEP;
+        P.ctl->stat_rounds += 1;
+      }
+      __syncthreads();
+      return;
+    }
   } else {
     for (unsigned int k = tid; k < L.ndeep; k += kBlock) {
       uint32_t word = ld_relaxed(&P.deep_fail[k >> 5]);
       L.st[P.deep_idx[k]] = (word >> (k & 31)) & 1 ? ST_FAIL : ST_PASS;
     }
   }
+  for (int i = tid; i < nadj; i += kBlock) R.adj[i] = P.adj[i];
   __syncthreads();
 
   if (tid < 64) {
@@ -342,9 +538,9 @@ __device__ void resolve_window(const Params &P, Lds &L) {
       const bool valid = j < s;
       const int st = valid ? L.st[j] : ST_FAIL;
       bool killed = st == ST_FAIL;
-      for (int J = 0; J < I; ++J) killed |= (L.adj[base + 64 * J + lane] & L.accm[J]) != 0;
+      for (int J = 0; J < I; ++J) killed |= (R.adj[base + 64 * J + lane] & R.accm[J]) != 0;
       unsigned long long alive = ballot(!killed);
-      const unsigned long long own = L.adj[base + 64 * I + lane];  // earlier neighbours in block
+      const unsigned long long own = R.adj[base + 64 * I + lane];  // earlier neighbours in block
       unsigned long long acc = 0;
       while (alive) {
         const int i = __builtin_ctzll(alive);
@@ -352,10 +548,10 @@ __device__ void resolve_window(const Params &P, Lds &L) {
         alive &= ~(1ull << i);
         alive &= ~ballot((own >> i) & 1);
       }
-      if (lane == 0) L.accm[I] = acc;
+      if (lane == 0) R.accm[I] = acc;
       const bool mine = (acc >> lane) & 1;
       const unsigned long long need = ballot(mine && st == ST_UNKNOWN);
-      if (mine) L.tlist[tcount + __builtin_popcountll(acc & lanemask_lt())] = L.s1w[j];
+      if (mine) R.tlist[tcount + __builtin_popcountll(acc & lanemask_lt())] = L.s1w[j];
       if (mine && st == ST_UNKNOWN) {
         const unsigned int k = ndeep + __builtin_popcountll(need & lanemask_lt());
         P.deep_word[k] = L.s1w[j];
@@ -387,7 +583,7 @@ __device__ void resolve_window(const Params &P, Lds &L) {
   const unsigned long long m0 = L.m0;
   unsigned long long room = P.capacity > m0 ? P.capacity - m0 : 0;
   const unsigned int nput = tcount < room ? tcount : (unsigned int)room;
-  for (unsigned int k = tid; k < nput; k += kBlock) P.code[m0 + k] = L.tlist[k];
+  for (unsigned int k = tid; k < nput; k += kBlock) P.code[m0 + k] = R.tlist[k];
 
   // Next window length: aim for `target` survivors from this window's density.
   const unsigned long long nwin = L.pe - L.p0;
@@ -437,6 +633,7 @@ __global__ void __launch_bounds__(kBlock) greedy_kernel(Params P) {
   unsigned long long my_near = 0, my_deep = 0, my_pairs = 0;
 
   init_tables(L.tab, P.n);
+  barrier_join(L, P.bar, P.ctl, P.spin_limit);
 
   for (;;) {
     if (tid == 0) {
@@ -456,43 +653,18 @@ __global__ void __launch_bounds__(kBlock) greedy_kernel(Params P) {
 
     // ---- A: near screen of [p0, pe0) against code[lo, m0) -----------------
     if (m0 > lo) {
-      const unsigned long long groups = (nwin + kGroup - 1) / kGroup;
-      const unsigned long long len = m0 - lo;
-      const unsigned long long ch = chunk_len(len, groups, nwaves);
-      const unsigned long long nch = (len + ch - 1) / ch;
-      for (unsigned long long it = gwave; it < groups * nch; it += nwaves) {
-        const unsigned long long c = it / groups, g = it % groups;
-        const unsigned long long b = m0 - c * ch;
-        const unsigned long long a = b > lo + ch ? b - ch : lo;
-        uint32_t x[kR];
-        uint32_t live = 0;
-#pragma unroll
-        for (int k = 0; k < kR; ++k) {
-          const unsigned long long off = g * kGroup + 64ull * k + lane;
-          x[k] = 0;
-          if (off < nwin) {
-            const uint32_t dead = ld_relaxed(&P.win_dead[off >> 5]);
-            if (!((dead >> (off & 31)) & 1)) {
-              live |= 1u << k;
-              x[k] = position_word(L.tab, P.n, P.ord, p0 + off);
-            }
-          }
-        }
-        if (!__any(live != 0)) continue;
-        unsigned long long scanned = 0;
-        const uint32_t conf = screen_range(P.code, a, b, x, live, d, &scanned);
-        my_near += scanned * kGroup;
-#pragma unroll
-        for (int k = 0; k < kR; ++k) {
-          if ((conf >> k) & 1) {
-            const unsigned long long off = g * kGroup + 64ull * k + lane;
-            __hip_atomic_fetch_or(&P.win_dead[off >> 5], 1u << (off & 31), __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-          }
-        }
+      const Split sp = make_split(nwin, m0 - lo);
+      const Source src{&L.tab, P.n, P.ord, p0, nullptr, P.win_dead};
+      for (unsigned long long it = blockIdx.x; it < sp.tiles * sp.parts; it += gridDim.x) {
+        const unsigned long long part = it / sp.tiles, tile = it % sp.tiles;
+        const unsigned long long b = m0 - part * sp.plen;
+        const unsigned long long a = b > lo + sp.plen ? b - sp.plen : lo;
+        const unsigned long long id0 = tile * kTile;
+        const uint32_t nc = (uint32_t)(nwin - id0 < (unsigned long long)kTile ? nwin - id0 : kTile);
+        my_near += tile_screen(L, src, P.code, (uint32_t)id0, nc, a, b, d);
       }
     }
-    grid_barrier(P.ctl, P.spin_limit);
+    grid_barrier(L, P.bar, P.ctl, P.spin_limit);
 
     // ---- C: survivor list (every workgroup) and in-window pairs ------------
     {
@@ -569,12 +741,12 @@ __global__ void __launch_bounds__(kBlock) greedy_kernel(Params P) {
         my_pairs += 64 * 64;
       }
     }
-    grid_barrier(P.ctl, P.spin_limit);
+    grid_barrier(L, P.bar, P.ctl, P.spin_limit);
 
     // ---- D / E rounds ------------------------------------------------------
     for (;;) {
       if (blockIdx.x == 0) resolve_window(P, L);
-      grid_barrier(P.ctl, P.spin_limit);
+      grid_barrier(L, P.bar, P.ctl, P.spin_limit);
       if (tid == 0) {
         L.action = ld_relaxed(&P.ctl->action);
         L.ndeep = ld_relaxed(&P.ctl->ndeep);
@@ -583,59 +755,38 @@ __global__ void __launch_bounds__(kBlock) greedy_kernel(Params P) {
       __syncthreads();
       if (L.action != ACT_DEEP || L.status != 0) break;
 
-      // ---- E: deep scan of tentatively accepted survivors vs code[0, lo) ----
-      const unsigned long long nd = L.ndeep;
-      const unsigned long long groups = (nd + kGroup - 1) / kGroup;
-      const unsigned long long ch = chunk_len(lo, groups, nwaves);
-      const unsigned long long nch = (lo + ch - 1) / ch;
-      for (unsigned long long it = gwave; it < groups * nch; it += nwaves) {
-        const unsigned long long c = it / groups, g = it % groups;
-        const unsigned long long b = lo - c * ch;
-        const unsigned long long a = b > ch ? b - ch : 0;
-        uint32_t x[kR];
-        uint32_t live = 0;
-#pragma unroll
-        for (int k = 0; k < kR; ++k) {
-          const unsigned long long idx = g * kGroup + 64ull * k + lane;
-          x[k] = 0;
-          if (idx < nd) {
-            const uint32_t failw = ld_relaxed(&P.deep_fail[idx >> 5]);
-            if (!((failw >> (idx & 31)) & 1)) {
-              live |= 1u << k;
-              x[k] = P.deep_word[idx];
-            }
-          }
-        }
-        if (!__any(live != 0)) continue;
-        unsigned long long scanned = 0;
-        const uint32_t conf = screen_range(P.code, a, b, x, live, d, &scanned);
-        my_deep += scanned * kGroup;
-#pragma unroll
-        for (int k = 0; k < kR; ++k) {
-          if ((conf >> k) & 1) {
-            const unsigned long long idx = g * kGroup + 64ull * k + lane;
-            __hip_atomic_fetch_or(&P.deep_fail[idx >> 5], 1u << (idx & 31), __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-          }
+      // ---- E: deep scan of the listed survivors against code[0, lo) ----------
+      {
+        const unsigned long long nd = L.ndeep;
+        const Split sp = make_split(nd, lo);
+        const Source src{&L.tab, P.n, P.ord, 0, P.deep_word, P.deep_fail};
+        for (unsigned long long it = blockIdx.x; it < sp.tiles * sp.parts; it += gridDim.x) {
+          const unsigned long long part = it / sp.tiles, tile = it % sp.tiles;
+          const unsigned long long b = lo - part * sp.plen;
+          const unsigned long long a = b > sp.plen ? b - sp.plen : 0;
+          const unsigned long long id0 = tile * kTile;
+          const uint32_t nc = (uint32_t)(nd - id0 < (unsigned long long)kTile ? nd - id0 : kTile);
+          my_deep += tile_screen(L, src, P.code, (uint32_t)id0, nc, a, b, d);
         }
       }
       if (tid == 0) L.round += 1;
-      grid_barrier(P.ctl, P.spin_limit);
+      grid_barrier(L, P.bar, P.ctl, P.spin_limit);
     }
     if (L.action == ACT_STOP || L.status != 0) break;
   }
 
-  if (lane == 0) {
+  if (tid == 0) {
     __hip_atomic_fetch_add(&P.ctl->stat_near, my_near, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_fetch_add(&P.ctl->stat_deep, my_deep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(&P.ctl->stat_pairs, my_pairs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  if (lane == 0)
+    __hip_atomic_fetch_add(&P.ctl->stat_pairs, my_pairs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (blockIdx.x == 0 && tid == 0 && P.count_out) *P.count_out = ld_relaxed(&P.ctl->m);
 }
 
 // Workspace initialisation (a kernel rather than memset, so that it can live
 // in captured graphs).
-__global__ void init_kernel(Ctl *ctl, uint32_t *win_dead, unsigned long long w0) {
+__global__ void init_kernel(Ctl *ctl, Bar *bar, uint32_t *win_dead, unsigned long long w0) {
   const unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
   if (i == 0) {
     Ctl c;
@@ -643,6 +794,9 @@ __global__ void init_kernel(Ctl *ctl, uint32_t *win_dead, unsigned long long w0)
     c.w = w0;
     *ctl = c;
   }
+  for (unsigned long long k = i; k < sizeof(Bar) / sizeof(unsigned int);
+       k += (unsigned long long)gridDim.x * blockDim.x)
+    reinterpret_cast<unsigned int *>(bar)[k] = 0;
   for (unsigned long long k = i; k < kWMax / 32; k += (unsigned long long)gridDim.x * blockDim.x)
     win_dead[k] = 0;
 }
@@ -795,7 +949,8 @@ int greedy_code_device_ex(int n, int d, int ordering, uint32_t *d_words, uint64_
 
   // Workspace: control block, window dead mask, adjacency, deep lists.
   const size_t off_ctl = 0;
-  const size_t off_dead = 256;
+  const size_t off_bar = 512;
+  const size_t off_dead = off_bar + ((sizeof(Bar) + 255) / 256) * 256;
   const size_t off_adj = off_dead + (kWMax / 32) * sizeof(uint32_t);
   const size_t off_dword = off_adj + kAdjWords * sizeof(unsigned long long);
   const size_t off_didx = off_dword + kSMax * sizeof(uint32_t);
@@ -813,6 +968,7 @@ int greedy_code_device_ex(int n, int d, int ordering, uint32_t *d_words, uint64_
   P.code = d_words;
   P.capacity = capacity;
   P.ctl = (Ctl *)(ws + off_ctl);
+  P.bar = (Bar *)(ws + off_bar);
   P.count_out = (unsigned long long *)d_count;
   P.win_dead = (uint32_t *)(ws + off_dead);
   P.adj = (unsigned long long *)(ws + off_adj);
@@ -824,10 +980,14 @@ int greedy_code_device_ex(int n, int d, int ordering, uint32_t *d_words, uint64_
   if (P.target > (unsigned int)kSMax) P.target = kSMax;
   if (P.target < 16) P.target = 16;
   P.spin_limit = kDefaultSpin;
+  // Resolve mode: graded orders reject many survivors deep in the code, so
+  // scanning every survivor once beats repeated tentative rounds there.
+  P.mode = (ordering == GC_GRLEX || ordering == GC_GREVLEX) ? MODE_DEEP_ALL : MODE_TENTATIVE;
+  if (tuning && tuning->resolve_mode) P.mode = tuning->resolve_mode == 2 ? MODE_DEEP_ALL : MODE_TENTATIVE;
   if (const char *env = getenv("GC_SPIN_LIMIT")) P.spin_limit = (unsigned int)strtoul(env, nullptr, 0);
 
   int status = GC_OK;
-  hipLaunchKernelGGL(init_kernel, dim3(8), dim3(256), 0, stream, P.ctl, P.win_dead,
+  hipLaunchKernelGGL(init_kernel, dim3(8), dim3(256), 0, stream, P.ctl, P.bar, P.win_dead,
                      (unsigned long long)kWMin);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipEventRecord(ev0, stream);

@@ -94,8 +94,12 @@ def test_host_entry_point():
 @pytest.mark.parametrize("o", ORDS)
 @pytest.mark.parametrize("tuning", [dict(near_depth=1), dict(near_depth=64, target_survivors=16),
                                     dict(near_depth=2 ** 63, target_survivors=1024),
-                                    dict(grid_blocks=1), dict(grid_blocks=7, near_depth=200)],
-                         ids=["near1", "near64_t16", "nearall_t1024", "grid1", "grid7"])
+                                    dict(grid_blocks=1), dict(grid_blocks=7, near_depth=200),
+                                    dict(near_depth=300, resolve_mode=1),
+                                    dict(near_depth=300, resolve_mode=2),
+                                    dict(grid_blocks=13, near_depth=1, resolve_mode=2)],
+                         ids=["near1", "near64_t16", "nearall_t1024", "grid1", "grid7",
+                              "tentative", "deepall", "grid13_deepall"])
 def test_tuning_does_not_change_the_code(o, tuning):
     for n, d in [(16, 3), (17, 4), (16, 5), (18, 6)]:
         words, _ = gpu_code(n, d, o, **tuning)
