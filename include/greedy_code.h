@@ -51,8 +51,15 @@ enum {
                           words that fit (device API) */
     GC_EDEVICE = -3,   /* a HIP call failed; see gc_last_error() */
     GC_ENOMEM = -4,    /* device or host allocation failed */
-    GC_ETIMEOUT = -5   /* a bounded device-side wait expired (no forward progress) */
+    GC_ETIMEOUT = -5,  /* a bounded device-side wait expired (no forward progress) */
+    GC_EBUSY = -6      /* server: the job has not finished yet */
 };
+
+/* Server job states (gc_server_poll). */
+enum { GC_JOB_WAITING = 0,   /* submitted, waiting for device memory */
+       GC_JOB_ADMITTED = 1,  /* published to the device queue */
+       GC_JOB_DONE = 2,      /* finished; words resident in the arena */
+       GC_JOB_FAILED = 3 };
 
 /* Work counters of one call (optional output).  checks_* count executed
  * distance checks (candidate x codeword pairs) by the kernel phase that ran
@@ -66,6 +73,9 @@ typedef struct gc_stats {
     uint64_t checks_deep;     /* deep-scan checks executed */
     uint64_t checks_pairs;    /* in-window pair checks executed */
     float kernel_ms;          /* device time of the construction kernel */
+    /* device time by phase (including the barrier that ends the phase):
+     * near screen, survivor list + conflict pairs, resolve, deep scans */
+    double near_ms, survivors_ms, resolve_ms, deep_ms;
 } gc_stats;
 
 /* Tuning knobs (optional input; zero fields take the built-in defaults). */
@@ -107,6 +117,64 @@ int greedy_code_device(int n, int d, int ordering, uint32_t *d_words, uint64_t c
 int greedy_code_device_ex(int n, int d, int ordering, uint32_t *d_words, uint64_t capacity,
                           uint64_t *d_count, void *hip_stream, const gc_tuning *tuning,
                           gc_stats *stats);
+
+/* One code of a batch.  Inputs: n, d, ordering, d_words (device array of
+ * `capacity` uint32, 16-byte aligned, caller-owned), d_count (device uint64 or
+ * NULL).  Outputs, filled in by greedy_code_batch: status (GC_OK or an error
+ * code), count (|C|), device_ms (device time from the moment a team picked the
+ * job up to its completion). */
+typedef struct gc_job {
+    int n, d, ordering;
+    uint32_t *d_words;
+    uint64_t capacity;
+    uint64_t *d_count;
+    int status;
+    uint64_t count;
+    double device_ms;
+} gc_job;
+
+/* Build many codes (BASELINE batched workload; no paper counterpart: the paper
+ * builds one code per run) in one persistent launch on `hip_stream`: the
+ * workgroups form `teams` teams (1, 2, 4 or 8; 0 = choose by job count) by
+ * XCD and each team pulls the next job from a device queue, so codes of
+ * uneven size share the GPU.  Every code is bit-identical to what
+ * greedy_code_device returns for it.  Returns GC_OK when every job succeeded,
+ * otherwise the first failing job's code (each job's status is set).
+ * kernel_ms (may be NULL) receives the device time of the launch. */
+int greedy_code_batch(gc_job *jobs, int njobs, int teams, void *hip_stream, float *kernel_ms);
+
+/* Job server (BASELINE served workload; no paper counterpart): continuous
+ * batching over one persistent launch.  Callers: anything that wants codes
+ * built as requests arrive.  A job is admitted once the device arena has room
+ * for its worst-case code (greedy_code_capacity(n, d) words); admitted jobs
+ * go to a queue in pinned host memory that the running kernel's teams pull
+ * from, so a job arriving while others build starts as soon as a team frees
+ * up.  Finished codes stay resident in the arena until released.  The
+ * kernel exits after about 0.1 s without work and is relaunched on demand.
+ * Not thread-safe across servers' destroy; every call on one server is
+ * serialised by an internal lock. */
+typedef struct gc_server gc_server;
+
+/* arena_bytes: device memory for resident codes; teams: 1, 2, 4 or 8. */
+int gc_server_create(size_t arena_bytes, int teams, gc_server **out);
+/* Queue a job; *ticket identifies it.  GC_ENOMEM if its worst-case code can
+ * never fit the arena. */
+int gc_server_submit(gc_server *srv, int n, int d, int ordering, uint64_t *ticket);
+/* *state = GC_JOB_*; *count (may be NULL) = |C| once done. */
+int gc_server_poll(gc_server *srv, uint64_t ticket, int *state, uint64_t *count);
+/* Device address of a finished job's words (valid until released). */
+int gc_server_words(gc_server *srv, uint64_t ticket, const uint32_t **d_words, uint64_t *count);
+/* Copy a finished job's words into host memory (cap words available). */
+int gc_server_fetch(gc_server *srv, uint64_t ticket, uint32_t *host_words, uint64_t cap,
+                    uint64_t *count);
+/* Work counters and device time of a finished job (either may be NULL). */
+int gc_server_stats(gc_server *srv, uint64_t ticket, gc_stats *stats, double *device_ms);
+/* Free a finished job's arena space (and admit waiting jobs). */
+int gc_server_release(gc_server *srv, uint64_t ticket);
+/* Wait until no job is waiting or building; timeout_ms < 0 waits forever. */
+int gc_server_drain(gc_server *srv, int timeout_ms);
+/* Stop the kernel and free everything (outstanding jobs are abandoned). */
+int gc_server_destroy(gc_server *srv);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *gc_last_error(void);

@@ -13,13 +13,16 @@ LIBRARY = os.path.join(HERE, "libgreedy_code.so")
 
 GC_LEX, GC_GRAY, GC_GRLEX, GC_GREVLEX = 0, 1, 2, 3
 ORDERINGS = {"lex": GC_LEX, "gray": GC_GRAY, "grlex": GC_GRLEX, "grevlex": GC_GREVLEX}
-GC_OK, GC_EINVAL, GC_ECAPACITY, GC_EDEVICE, GC_ENOMEM, GC_ETIMEOUT = 0, -1, -2, -3, -4, -5
+GC_OK, GC_EINVAL, GC_ECAPACITY, GC_EDEVICE, GC_ENOMEM, GC_ETIMEOUT, GC_EBUSY = 0, -1, -2, -3, -4, -5, -6
 ERROR_NAMES = {GC_EINVAL: "GC_EINVAL", GC_ECAPACITY: "GC_ECAPACITY", GC_EDEVICE: "GC_EDEVICE",
-               GC_ENOMEM: "GC_ENOMEM", GC_ETIMEOUT: "GC_ETIMEOUT"}
+               GC_ENOMEM: "GC_ENOMEM", GC_ETIMEOUT: "GC_ETIMEOUT", GC_EBUSY: "GC_EBUSY"}
+GC_JOB_WAITING, GC_JOB_ADMITTED, GC_JOB_DONE, GC_JOB_FAILED = 0, 1, 2, 3
 
 # Every symbol declared in include/greedy_code.h.
 EXPORTS = ["greedy_code_capacity", "greedy_code", "greedy_code_device", "greedy_code_device_ex",
-           "gc_last_error", "gc_version"]
+           "greedy_code_batch", "gc_server_create", "gc_server_submit", "gc_server_poll",
+           "gc_server_words", "gc_server_fetch", "gc_server_stats", "gc_server_release",
+           "gc_server_drain", "gc_server_destroy", "gc_last_error", "gc_version"]
 
 
 class GreedyCodeError(RuntimeError):
@@ -32,7 +35,9 @@ class GcStats(ctypes.Structure):
     _fields_ = [("count", ctypes.c_uint64), ("windows", ctypes.c_uint64),
                 ("resolve_rounds", ctypes.c_uint64), ("survivors", ctypes.c_uint64),
                 ("checks_near", ctypes.c_uint64), ("checks_deep", ctypes.c_uint64),
-                ("checks_pairs", ctypes.c_uint64), ("kernel_ms", ctypes.c_float)]
+                ("checks_pairs", ctypes.c_uint64), ("kernel_ms", ctypes.c_float),
+                ("near_ms", ctypes.c_double), ("survivors_ms", ctypes.c_double),
+                ("resolve_ms", ctypes.c_double), ("deep_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -42,6 +47,13 @@ class GcTuning(ctypes.Structure):
     _fields_ = [("near_depth", ctypes.c_uint64), ("target_survivors", ctypes.c_uint32),
                 ("grid_blocks", ctypes.c_uint32), ("resolve_mode", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32)]
+
+
+class GcJob(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("d", ctypes.c_int), ("ordering", ctypes.c_int),
+                ("d_words", ctypes.c_void_p), ("capacity", ctypes.c_uint64),
+                ("d_count", ctypes.c_void_p), ("status", ctypes.c_int), ("count", ctypes.c_uint64),
+                ("device_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -68,6 +80,28 @@ def load():
                                           ctypes.c_uint64, vp, vp, ctypes.POINTER(GcTuning),
                                           ctypes.POINTER(GcStats)]
     lib.greedy_code_device_ex.restype = ctypes.c_int
+    lib.greedy_code_batch.argtypes = [ctypes.POINTER(GcJob), ctypes.c_int, ctypes.c_int, vp,
+                                      ctypes.POINTER(ctypes.c_float)]
+    lib.greedy_code_batch.restype = ctypes.c_int
+    lib.gc_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
+    lib.gc_server_create.restype = ctypes.c_int
+    lib.gc_server_submit.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, u64p]
+    lib.gc_server_submit.restype = ctypes.c_int
+    lib.gc_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), u64p]
+    lib.gc_server_poll.restype = ctypes.c_int
+    lib.gc_server_words.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p), u64p]
+    lib.gc_server_words.restype = ctypes.c_int
+    lib.gc_server_fetch.argtypes = [vp, ctypes.c_uint64, u32p, ctypes.c_uint64, u64p]
+    lib.gc_server_fetch.restype = ctypes.c_int
+    lib.gc_server_stats.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(GcStats),
+                                    ctypes.POINTER(ctypes.c_double)]
+    lib.gc_server_stats.restype = ctypes.c_int
+    lib.gc_server_release.argtypes = [vp, ctypes.c_uint64]
+    lib.gc_server_release.restype = ctypes.c_int
+    lib.gc_server_drain.argtypes = [vp, ctypes.c_int]
+    lib.gc_server_drain.restype = ctypes.c_int
+    lib.gc_server_destroy.argtypes = [vp]
+    lib.gc_server_destroy.restype = ctypes.c_int
     lib.gc_last_error.argtypes = []
     lib.gc_last_error.restype = ctypes.c_char_p
     lib.gc_version.argtypes = []
@@ -147,3 +181,80 @@ def device_code(n: int, d: int, ordering, device="cuda", **tuning):
     stats = greedy_code_device_ex(n, d, ordering, words, count, **tuning)
     m = int(count.item())
     return words[:m], stats
+
+
+def greedy_code_batch(instances, teams=0, stream=None, device="cuda"):
+    """Build several codes in one persistent launch.  ``instances``: list of
+    (n, d, ordering).  Returns (list of uint32 CUDA tensors trimmed to |C|,
+    list of per-job dicts with status/count/device_ms, kernel_ms)."""
+    import torch
+    jobs = (GcJob * len(instances))()
+    bufs = []
+    for i, (n, d, o) in enumerate(instances):
+        cap = greedy_code_capacity(n, d)
+        w = torch.empty(cap, dtype=torch.int32, device=device)
+        c = torch.zeros(1, dtype=torch.int64, device=device)
+        bufs.append((w, c))
+        jobs[i].n, jobs[i].d, jobs[i].ordering = n, d, _ordering(o)
+        jobs[i].d_words, jobs[i].capacity, jobs[i].d_count = w.data_ptr(), cap, c.data_ptr()
+    ms = ctypes.c_float()
+    rc = load().greedy_code_batch(jobs, len(instances), teams, _stream_ptr(stream), ctypes.byref(ms))
+    _check(rc)
+    out = [w[: int(jobs[i].count)] for i, (w, _) in enumerate(bufs)]
+    info = [{"status": jobs[i].status, "count": int(jobs[i].count), "device_ms": jobs[i].device_ms}
+            for i in range(len(instances))]
+    return out, info, ms.value
+
+
+class Server:
+    """Thin wrapper of the gc_server_* entry points."""
+
+    def __init__(self, arena_bytes=1 << 30, teams=8):
+        self._h = ctypes.c_void_p()
+        _check(load().gc_server_create(arena_bytes, teams, ctypes.byref(self._h)))
+
+    def submit(self, n, d, ordering) -> int:
+        t = ctypes.c_uint64()
+        _check(load().gc_server_submit(self._h, n, d, _ordering(ordering), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket):
+        st, cnt = ctypes.c_int(), ctypes.c_uint64()
+        _check(load().gc_server_poll(self._h, ticket, ctypes.byref(st), ctypes.byref(cnt)))
+        return st.value, cnt.value
+
+    def fetch(self, ticket) -> np.ndarray:
+        st, cnt = self.poll(ticket)
+        if st == GC_JOB_FAILED:
+            _check(load().gc_server_words(self._h, ticket, ctypes.byref(ctypes.c_void_p()),
+                                          ctypes.byref(ctypes.c_uint64())))
+        out = np.zeros(max(cnt, 1), dtype=np.uint32)
+        got = ctypes.c_uint64()
+        _check(load().gc_server_fetch(self._h, ticket,
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), out.size,
+                                      ctypes.byref(got)))
+        return out[: got.value].copy()
+
+    def stats(self, ticket) -> dict:
+        st, ms = GcStats(), ctypes.c_double()
+        _check(load().gc_server_stats(self._h, ticket, ctypes.byref(st), ctypes.byref(ms)))
+        d = st.as_dict()
+        d["device_ms"] = ms.value
+        return d
+
+    def release(self, ticket):
+        _check(load().gc_server_release(self._h, ticket))
+
+    def drain(self, timeout_ms=-1):
+        _check(load().gc_server_drain(self._h, timeout_ms))
+
+    def close(self):
+        if self._h:
+            load().gc_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

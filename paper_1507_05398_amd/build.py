@@ -5,7 +5,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", "greedy_code.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "greedy_code.hip"), os.path.join(HERE, "csrc", "server.hip")]
 HEADERS = [os.path.join(ROOT, "include", "greedy_code.h")]
 LIBRARY = os.path.join(HERE, "libgreedy_code.so")
 ARCH = "gfx950"
@@ -24,7 +24,7 @@ def build(verbose: bool = False) -> str:
            # packed fp32 instructions stay off (see the project notes on gfx950)
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wall", "-Wno-unused-command-line-argument",
-           "-I", os.path.join(ROOT, "include"),
+           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
            "-o", LIBRARY + ".tmp", *SOURCES]
     if verbose:
         print(" ".join(cmd))

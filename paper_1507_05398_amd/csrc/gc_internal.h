@@ -1,0 +1,98 @@
+// gc_internal.h -- structures shared by the persistent kernel and the host
+// code of libgreedy_code.so (single code, batch and server entry points).
+// Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace gcimpl {
+
+constexpr int kBlock = 1024;   // threads per workgroup
+constexpr int kMaxXcd = 16;    // XCD ids are taken modulo this
+constexpr int kMaxTeams = 8;
+
+// One code to build.  In batch mode the array lives in device memory, in
+// server mode in pinned host memory (coherent, mapped): the device reads the
+// inputs once and writes the outputs, `done` last.
+struct Job {
+  // inputs
+  int n, d, ord, mode;            // mode: 0 by ordering, 1 tentative, 2 deep-scan all survivors
+  unsigned long long near_depth;  // 0: default
+  unsigned int target;            // 0: default
+  unsigned int pad0;
+  uint32_t *code;                 // device array of `capacity` words (16-byte aligned)
+  unsigned long long capacity;
+  unsigned long long *count;      // device counter written at completion (may be null)
+  // outputs
+  unsigned long long out_count;
+  unsigned long long windows, rounds, survivors, chk_near, chk_deep, chk_pairs;
+  unsigned long long ticks_near, ticks_surv, ticks_resolve, ticks_deep;  // phase time (100 MHz)
+  unsigned long long t_claim, t_done;  // device wall clock (100 MHz) at claim / completion
+  int status;
+  unsigned int done;              // 0 pending, 1 finished (written last)
+};
+
+// Job queue.  `submitted` and `shutdown` may live in host memory (server);
+// `claimed` and `abort` always live in device memory.
+struct HostQueue {
+  unsigned int submitted;   // number of jobs visible to the device
+  unsigned int shutdown;    // host sets 1: the kernel exits when idle
+  unsigned int pad[62];
+};
+
+struct DevQueue {
+  unsigned int claimed;     // next job index to claim
+  unsigned int completed;   // jobs finished
+  int abort;                // a bounded wait expired: every team stops
+  unsigned int launches;
+  unsigned int pad[60];
+};
+
+// Per-team instance state.
+struct Ctl {
+  unsigned long long m;   // committed words
+  unsigned long long p;   // start of the next window
+  unsigned long long w;   // length of the next window
+  int status;
+  int action;
+  unsigned int ndeep;
+  int job;                // job being built, -1 when the team stops
+  unsigned long long stat_windows, stat_rounds, stat_surv, stat_near, stat_deep, stat_pairs;
+  unsigned long long ticks[4];   // near screen, survivors+pairs, resolve, deep scan
+  unsigned int pad[24];
+};
+
+// Barrier state: per XCD a counter, a generation and the member count (each
+// on its own 256-byte line); per team a counter and generation for the XCD
+// leaders; a one-time join count.
+struct Bar {
+  unsigned int join_count;
+  unsigned int pad0[63];
+  unsigned int xcd[kMaxXcd][64];     // [0] count, [1] generation, [2] members
+  unsigned int team[kMaxTeams][64];  // [0] count, [1] generation, [2] members, [3] xcds
+};
+
+struct Params {
+  Job *jobs;
+  HostQueue *hq;
+  DevQueue *dq;
+  Bar *bar;
+  int njobs_fixed;               // batch: number of jobs; server: -1 (read hq->submitted)
+  int nteams;
+  unsigned int spin_limit;       // bounded waits inside a job
+  unsigned int idle_limit;       // server: polls of an empty queue before the kernel exits
+  char *team_ws;                 // per-team workspace, team_ws_stride bytes each
+  unsigned long long team_ws_stride;
+};
+
+size_t team_workspace_bytes();
+int device_info(int dev, int *cus, int *coop, int *blocks_per_cu);
+hipError_t launch_persistent(const Params &P, unsigned int grid, hipStream_t stream);
+hipError_t launch_init(Bar *bar, DevQueue *dq, int reset_queue, hipStream_t stream);
+int fail(int code, const char *fmt, ...);
+extern thread_local std::string g_error;
+
+}  // namespace gcimpl

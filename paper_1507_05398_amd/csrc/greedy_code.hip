@@ -5,38 +5,39 @@
 // append a vector to the code C when popcount(x XOR c) >= d for every word c
 // already in C (section "Hamming Distance").  The result is one ordered list.
 //
-// Device design (one cooperative persistent launch per code):
+// Execution model: one cooperative persistent kernel.  Its workgroups form
+// teams by XCD (1, 2, 4 or 8 teams); a team pulls jobs (codes to build) from
+// a queue and builds each with team-wide barriers.  A single code is a queue
+// of one job on one team that spans the GPU; a batch pre-fills the queue; the
+// server feeds the queue from host memory while the kernel runs.
 //
-//   The ordering is cut into windows of consecutive positions.  For a window
-//   starting with m0 committed words:
+// Building one code: the ordering is cut into windows of consecutive
+// positions.  For a window starting with m0 committed words:
 //
 //   A  near screen   every window candidate is compared with the newest
-//                    `near_depth` committed words (2-D work items: 256
-//                    candidates x a code chunk, newest chunk first); a conflict
-//                    sets the candidate's bit in a window "dead" mask.
+//                    `near_depth` committed words; a conflict sets the
+//                    candidate's bit in the window "dead" mask.
 //   C  survivors     every workgroup rebuilds the ordered survivor list in LDS
-//                    (capped at kSMax, the window is cut at the cap) and the
-//                    grid computes the in-window conflict graph among survivors
-//                    as 64x64-bit tiles (earlier-neighbour masks).
+//                    (capped at kSMax; the window is cut at the cap) and the
+//                    team computes the in-window conflict graph among the
+//                    survivors as 64x64-bit tiles (earlier-neighbour masks).
 //   D  resolve       one wave computes the lexicographically first maximal
 //                    independent set of the survivor graph in position order,
-//                    which is exactly sequential greedy restricted to the
-//                    window, treating survivors whose deep status is unknown as
+//                    which is sequential greedy restricted to the window,
+//                    treating survivors whose deep status is unknown as
 //                    passing.
-//   E  deep scan     tentatively accepted survivors whose status is unknown
-//                    are compared with the older code words [0, m0-near_depth)
-//                    (2-D items again); D then runs again with the new facts.
-//                    When every tentatively accepted survivor is known to pass,
-//                    the set is the greedy result for the window: it is
-//                    appended to the code and the next window starts.
+//   E  deep scan     survivors whose status is needed are compared with the
+//                    older words [0, m0 - near_depth); D then runs again with
+//                    the new facts.  When every tentatively accepted survivor
+//                    is known to pass, the set is the greedy result for the
+//                    window: it is appended to the code.
 //
-//   Between phases the grid synchronises with a bounded-wait barrier.  The
-//   paper launched two kernels per candidate and copied |C| to the host each
-//   time (sections "Parallel Implementation", "Removing Wasted Threads",
-//   "Dynamic Parallelism"); here |C| stays on the device and one launch covers
-//   all 2^n positions.  Its "selective kernel launch" (check part of the code
-//   first, the rest only if that passes) becomes the near screen / deep scan
-//   split, reordered newest-first.
+// The paper launched two kernels per candidate and copied |C| to the host
+// each time (sections "Parallel Implementation", "Removing Wasted Threads",
+// "Dynamic Parallelism"); here |C| stays on the device and one launch covers
+// every position of every job.  Its "selective kernel launch" (check part of
+// the code first, the rest only if that passes) becomes the near screen /
+// deep scan split, reordered newest-first.
 //
 // Distance checks run on the vector ALUs: v_xor_b32, v_bcnt_u32_b32 and
 // v_min3_u32 (2.5 instructions per check).  No matrix cores: this is bit-packed
@@ -51,88 +52,81 @@
 
 #include <mutex>
 #include <string>
+#include <vector>
 
+#include "gc_internal.h"
 #include "greedy_code.h"
 
-#define GC_VERSION_STRING "greedy_code 0.1.0 (gfx950)"
+#define GC_VERSION_STRING "greedy_code 0.2.0 (gfx950)"
 
 namespace gcimpl {
 
-constexpr int kBlock = 1024;                          // threads per workgroup
 constexpr int kWaves = kBlock / 64;                   // waves per workgroup
-constexpr int kTile = 256;                            // candidates per screen tile (4 rows of 64)
+constexpr int kTile = 1024;                           // candidates per screen tile (16 rows of 64)
 constexpr int kRows = kTile / 64;
-constexpr int kSeg = 64 * kWaves;                     // code words per screen segment (64 per wave)
-constexpr int kMaxXcd = 16;
+constexpr int kSegMax = 64 * kWaves;                  // longest code segment staged at once
 constexpr int kSMax = 1024;                           // survivors per window (resolve capacity)
 constexpr int kNb = kSMax / 64;                       // survivor blocks of 64
 constexpr int kAdjWords = 64 * kNb * (kNb + 1) / 2;   // lower-triangular block adjacency
 constexpr unsigned long long kWMin = 256;
 constexpr unsigned long long kWMax = 1ull << 18;
+constexpr int kWordsPerThread = (int)(kWMax / 32 / kBlock);  // window mask words per thread
 constexpr unsigned int kDefaultTarget = 768;
 constexpr unsigned long long kDefaultNear = 16384;
 constexpr unsigned int kDefaultSpin = 1u << 25;
 
 enum : int { ST_UNKNOWN = 0, ST_PASS = 1, ST_FAIL = 2 };
 enum : int { ACT_NEXT = 0, ACT_DEEP = 1, ACT_STOP = 2 };
-enum : int { MODE_TENTATIVE = 1, MODE_DEEP_ALL = 2 };
+enum : int { MODE_AUTO = 0, MODE_TENTATIVE = 1, MODE_DEEP_ALL = 2 };
 
-// Grid barrier state: one counter/generation pair per XCD (each on its own
-// 256-byte line) and one pair across XCD leaders.
-struct Bar {
-  unsigned int join_count;   // one-time membership count
-  unsigned int top_count;
-  unsigned int top_gen;
-  unsigned int pad0[61];
-  unsigned int xcd[kMaxXcd][64];   // [x][0] count, [x][1] generation, [x][2] members
-};
-
-struct Ctl {
-  unsigned long long m;   // committed words
-  unsigned long long p;   // start of the next window
-  unsigned long long w;   // length of the next window
-  unsigned int pad_bar[2];
-  int status;
-  int action;
-  unsigned int ndeep;
-  unsigned int pad;
-  unsigned long long stat_windows, stat_rounds, stat_surv, stat_near, stat_deep, stat_pairs;
-};
-
-struct Params {
-  int n, d, ord, mode;
-  unsigned long long total;   // 2^n
-  uint32_t *code;
-  unsigned long long capacity;
+// Per-team workspace, carved out of one buffer.
+struct TeamWs {
   Ctl *ctl;
-  Bar *bar;
-  unsigned long long *count_out;
-  uint32_t *win_dead;             // kWMax / 32 words
-  unsigned long long *adj;        // kAdjWords
-  uint32_t *deep_word;            // kSMax
-  uint32_t *deep_idx;             // kSMax
-  uint32_t *deep_fail;            // kSMax / 32
-  unsigned long long near_depth;
-  unsigned int target;
-  unsigned int spin_limit;
+  uint32_t *win_dead;        // kWMax / 32
+  unsigned long long *adj;   // kAdjWords
+  uint32_t *deep_word;       // kSMax
+  uint32_t *deep_idx;        // kSMax
+  uint32_t *deep_fail;       // kSMax / 32
 };
+
+constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+constexpr size_t kOffCtl = 0;
+constexpr size_t kOffDead = align256(sizeof(Ctl));
+constexpr size_t kOffAdj = kOffDead + align256(kWMax / 32 * sizeof(uint32_t));
+constexpr size_t kOffDword = kOffAdj + align256(kAdjWords * sizeof(unsigned long long));
+constexpr size_t kOffDidx = kOffDword + align256(kSMax * sizeof(uint32_t));
+constexpr size_t kOffDfail = kOffDidx + align256(kSMax * sizeof(uint32_t));
+constexpr size_t kTeamWsBytes = kOffDfail + align256(kSMax / 32 * sizeof(uint32_t));
+
+__host__ __device__ inline TeamWs team_ws(char *base) {
+  TeamWs w;
+  w.ctl = reinterpret_cast<Ctl *>(base + kOffCtl);
+  w.win_dead = reinterpret_cast<uint32_t *>(base + kOffDead);
+  w.adj = reinterpret_cast<unsigned long long *>(base + kOffAdj);
+  w.deep_word = reinterpret_cast<uint32_t *>(base + kOffDword);
+  w.deep_idx = reinterpret_cast<uint32_t *>(base + kOffDidx);
+  w.deep_fail = reinterpret_cast<uint32_t *>(base + kOffDfail);
+  return w;
+}
+
+size_t team_workspace_bytes() { return kTeamWsBytes; }
 
 struct Tables {
   uint32_t binom[33][33];              // C(a, b)
   unsigned long long off[34];          // off[w] = number of words of weight < w
 };
 
-// Screen tile: candidate words and ids (double-buffered for compaction), code
-// segment (double-buffered), per-wave conflict masks.
+// Screen tile: code segment (double-buffered), candidate words and ids
+// (double-buffered for compaction), per-wave conflict masks.
 struct TileLds {
-  alignas(16) uint32_t seg[2][kSeg];
+  alignas(16) uint32_t seg[2][kSegMax];
   uint32_t cw[2][kTile];
   uint32_t ci[2][kTile];
   unsigned long long killw[kWaves][kRows];
   unsigned int wcnt[kWaves];
 };
 
-// In-window resolve (workgroup 0 only).
+// In-window resolve (team rank 0 only).
 struct ResolveLds {
   unsigned long long adj[kAdjWords];   // survivor adjacency (earlier-neighbour masks)
   unsigned long long accm[kNb];        // accepted mask per block
@@ -143,10 +137,18 @@ struct Lds {
   uint32_t s1w[kSMax];                 // window survivors, in position order
   uint8_t st[kSMax];                   // deep status of each survivor (resolve only)
   Tables tab;
+  // job
+  int job, n, d, ord, mode;
+  uint32_t *code;
+  unsigned long long capacity, total, near_depth;
+  unsigned int target;
+  // window
   unsigned long long p0, m0, w, pe, lo;
   unsigned int s, s_tot, ndeep, round, tcount, truncated;
-  int status, action;
-  unsigned int xcd, xcd_members, nxcd;
+  int status, action, abort;
+  // team
+  unsigned int xcd, xcd_members, team, team_rank, team_size, team_xcds;
+  unsigned long long cnt_near, cnt_deep, cnt_pairs;   // this workgroup's executed checks
   unsigned int wsum[kWaves];
   union alignas(16) {
     TileLds t;
@@ -167,20 +169,22 @@ __device__ __forceinline__ uint32_t dist(uint32_t a, uint32_t b) { return __buil
 
 __device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
 
-__device__ __forceinline__ unsigned int lane_id() { return __lane_id(); }
-
 __device__ __forceinline__ unsigned long long lanemask_lt() {
-  unsigned int l = lane_id();
+  const unsigned int l = __lane_id();
   return l ? (~0ull >> (64 - l)) : 0ull;
 }
 
 template <typename T>
-__device__ __forceinline__ T ld_acquire(T *p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
 __device__ __forceinline__ T ld_relaxed(T *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_sys(T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+template <typename T>
+__device__ __forceinline__ void st_sys(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __device__ __forceinline__ void set_status(Ctl *ctl, int code) {
@@ -189,84 +193,105 @@ __device__ __forceinline__ void set_status(Ctl *ctl, int code) {
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ void set_abort(const Params &P) {
+  __hip_atomic_store(&P.dq->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ unsigned int xcc_id() {
   unsigned int v;
   asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(v));
   return v & (kMaxXcd - 1);
 }
 
-// Bounded spin until *p != old; records GC_ETIMEOUT and gives up after
-// spin_limit polls so that no wait can hang the device.
-__device__ __forceinline__ void wait_change(unsigned int *p, unsigned int old, Ctl *ctl,
-                                            unsigned int spin_limit) {
+// Bounded spin until *p != old.  Gives up after `limit` polls and raises the
+// kernel-wide abort flag, so that no wait can hang the device.
+__device__ __forceinline__ bool wait_change(unsigned int *p, unsigned int old, const Params &P,
+                                            unsigned int limit) {
   unsigned int spins = 0;
   while (ld_relaxed(p) == old) {
     __builtin_amdgcn_s_sleep(1);
-    if (++spins > spin_limit) {
-      set_status(ctl, GC_ETIMEOUT);
-      break;
+    if (++spins > limit) {
+      set_abort(P);
+      return false;
     }
   }
+  return true;
 }
 
-// One-time registration: every workgroup counts itself on its XCD, then all
-// wait until the whole grid has registered, so that each XCD leader knows how
-// many workgroups to expect (no assumption about the block -> XCD mapping).
-__device__ void barrier_join(Lds &L, Bar *B, Ctl *ctl, unsigned int spin_limit) {
+// ---------------------------------------------------------------------------
+// Teams and barriers
+// ---------------------------------------------------------------------------
+
+// One-time registration: every workgroup counts itself on its XCD and takes a
+// rank in its team (team = XCD id mod nteams), then all wait until the whole
+// grid has registered.  No assumption is made about the block -> XCD mapping.
+__device__ void team_join(Lds &L, const Params &P) {
   if (threadIdx.x == 0) {
+    Bar *B = P.bar;
     const unsigned int x = xcc_id();
+    const unsigned int t = x % (unsigned int)P.nteams;
     __hip_atomic_fetch_add(&B->xcd[x][2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned int rank =
+        __hip_atomic_fetch_add(&B->team[t][2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_fetch_add(&B->join_count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     unsigned int spins = 0;
     while (ld_relaxed(&B->join_count) < gridDim.x) {
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > spin_limit) {
-        set_status(ctl, GC_ETIMEOUT);
+      if (++spins > P.spin_limit) {
+        set_abort(P);
         break;
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     unsigned int nx = 0;
-    for (int i = 0; i < kMaxXcd; ++i) nx += ld_relaxed(&B->xcd[i][2]) > 0;
+    for (int i = 0; i < kMaxXcd; ++i)
+      if ((unsigned int)i % (unsigned int)P.nteams == t && ld_relaxed(&B->xcd[i][2]) > 0) ++nx;
     L.xcd = x;
     L.xcd_members = ld_relaxed(&B->xcd[x][2]);
-    L.nxcd = nx;
+    L.team = t;
+    L.team_rank = rank;
+    L.team_size = ld_relaxed(&B->team[t][2]);
+    L.team_xcds = nx;
+    L.abort = ld_relaxed(&P.dq->abort);
   }
   __syncthreads();
 }
 
-// Grid-wide barrier for a cooperative launch, two levels.  Workgroups of one
-// XCD meet on that XCD's counter; the last to arrive (the XCD leader) makes
-// the XCD's writes visible device-wide (release), meets the other leaders,
-// acquires, and releases its XCD.  Every workgroup then acquires at agent
-// scope before reading data written elsewhere.  All waits are bounded.
-__device__ void grid_barrier(Lds &L, Bar *B, Ctl *ctl, unsigned int spin_limit) {
+// Team-wide barrier, two levels.  Workgroups of one XCD meet on that XCD's
+// counter; the last to arrive (the XCD leader) makes the XCD's writes visible
+// device-wide (release), meets the other leaders of the team, acquires, and
+// releases its XCD.  Every workgroup then acquires at agent scope before it
+// reads data written elsewhere.  Waits are bounded by `limit` polls.
+__device__ void team_barrier(Lds &L, const Params &P, unsigned int limit) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
+    Bar *B = P.bar;
     unsigned int *xc = &B->xcd[L.xcd][0];
     unsigned int *xg = &B->xcd[L.xcd][1];
     const unsigned int g = ld_relaxed(xg);
     const unsigned int a = __hip_atomic_fetch_add(xc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (a + 1 == L.xcd_members) {
       __hip_atomic_store(xc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned int tg = ld_relaxed(&B->top_gen);
-      const unsigned int b =
-          __hip_atomic_fetch_add(&B->top_count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      if (b + 1 == L.nxcd) {
-        __hip_atomic_store(&B->top_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&B->top_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      unsigned int *tc = &B->team[L.team][0];
+      unsigned int *tgp = &B->team[L.team][1];
+      const unsigned int tg = ld_relaxed(tgp);
+      const unsigned int b = __hip_atomic_fetch_add(tc, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (b + 1 == L.team_xcds) {
+        __hip_atomic_store(tc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(tgp, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       } else {
-        wait_change(&B->top_gen, tg, ctl, spin_limit);
+        wait_change(tgp, tg, P, limit);
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       __builtin_amdgcn_s_waitcnt(0);
       __hip_atomic_fetch_add(xg, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      wait_change(xg, g, ctl, spin_limit);
+      wait_change(xg, g, P, limit);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __builtin_amdgcn_s_waitcnt(0);
+    L.abort = ld_relaxed(&P.dq->abort);
   }
   __syncthreads();
 }
@@ -278,10 +303,10 @@ __device__ void grid_barrier(Lds &L, Bar *B, Ctl *ctl, unsigned int spin_limit) 
 // The r-th (from 0) n-bit integer of weight k in increasing order
 // (combinatorial number system: the top bit is the largest b with
 // C(b, k) <= r).
-__device__ __forceinline__ uint32_t unrank_weight(const Tables &L, unsigned long long r, int k, int n) {
+__device__ __forceinline__ uint32_t unrank_weight(const Tables &T, unsigned long long r, int k, int n) {
   uint32_t x = 0;
   for (int b = n - 1; b >= 0 && k > 0; --b) {
-    unsigned long long c = L.binom[b][k];
+    const unsigned long long c = T.binom[b][k];
     if (r >= c) {
       x |= 1u << b;
       r -= c;
@@ -291,22 +316,22 @@ __device__ __forceinline__ uint32_t unrank_weight(const Tables &L, unsigned long
   return x;
 }
 
-__device__ __forceinline__ uint32_t position_word(const Tables &L, int n, int ord, unsigned long long p) {
+__device__ __forceinline__ uint32_t position_word(const Tables &T, int n, int ord, unsigned long long p) {
   if (ord == GC_LEX) return (uint32_t)p;
   if (ord == GC_GRAY) return (uint32_t)(p ^ (p >> 1));
   int w = 0;
-  while (w < n && L.off[w + 1] <= p) ++w;
-  unsigned long long r = p - L.off[w];
-  if (ord == GC_GRLEX) return unrank_weight(L, r, w, n);
+  while (w < n && T.off[w + 1] <= p) ++w;
+  const unsigned long long r = p - T.off[w];
+  if (ord == GC_GRLEX) return unrank_weight(T, r, w, n);
   // GREVLEX: inside weight w, the r-th word is the bit-reversed complement of
   // the r-th weight-(n-w) integer (complement reverses the increasing order,
   // bit reversal turns "differs first at the top" into "at the bottom").
-  uint32_t y = unrank_weight(L, r, n - w, n);
-  uint32_t mask = n == 32 ? 0xffffffffu : ((1u << n) - 1u);
+  const uint32_t y = unrank_weight(T, r, n - w, n);
+  const uint32_t mask = n == 32 ? 0xffffffffu : ((1u << n) - 1u);
   return __builtin_bitreverse32(~y & mask) >> (32 - n);
 }
 
-// Fill the binomial and weight-offset tables (whole workgroup).
+// Fill the binomial and weight-offset tables for length n (whole workgroup).
 __device__ void init_tables(Tables &T, int n) {
   for (int i = threadIdx.x; i < 33 * 33; i += blockDim.x) {
     const int a = i / 33, b = i % 33;
@@ -346,21 +371,22 @@ struct Source {
     return words ? words[id] : position_word(*tab, n, ord, p0 + id);
   }
   __device__ bool is_dead(uint32_t id) const { return (ld_relaxed(&dead[id >> 5]) >> (id & 31)) & 1; }
+  __device__ uint32_t dead_word(uint32_t id) const { return ld_relaxed(&dead[id >> 5]); }
   __device__ void kill(uint32_t id) const {
     __hip_atomic_fetch_or(&dead[id >> 5], 1u << (id & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 };
 
-// Workgroup compaction: threads of the first kRows waves offer (keep, word,
-// id); kept entries go densely and in order to buffer dst.  Returns the count.
+// Workgroup compaction: thread t offers entry t (keep, word, id); kept
+// entries go densely and in order to buffer dst.  Returns the count.
 __device__ unsigned int tile_compact(TileLds &T, int dst, bool keep, uint32_t word, uint32_t id) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const unsigned long long m = ballot(keep);
-  if (lane == 0 && wave < kRows) T.wcnt[wave] = (unsigned int)__builtin_popcountll(m);
+  if (lane == 0) T.wcnt[wave] = (unsigned int)__builtin_popcountll(m);
   __syncthreads();
   unsigned int base = 0, total = 0;
 #pragma unroll
-  for (int w = 0; w < kRows; ++w) {
+  for (int w = 0; w < kWaves; ++w) {
     if (w < wave) base += T.wcnt[w];
     total += T.wcnt[w];
   }
@@ -373,43 +399,47 @@ __device__ unsigned int tile_compact(TileLds &T, int dst, bool keep, uint32_t wo
   return total;
 }
 
-// One wave against its 64 words of the staged segment, ROWS rows of 64 live
-// candidates; m[r] gets the lanes of row r closer than d to one of the words.
-template <int ROWS>
-__device__ __forceinline__ void segment_rows(const TileLds &T, int cur, int buf, unsigned int live,
-                                             uint32_t d, unsigned long long (&m)[kRows]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t x[ROWS], acc[ROWS];
+// One row of 64 live candidates against 64 staged words; returns the lanes
+// whose candidate is closer than d to one of them.
+__device__ __forceinline__ unsigned long long row_chunk(const TileLds &T, int cur, int buf, unsigned int row,
+                                                        unsigned int chunk, unsigned int live, uint32_t d) {
+  const unsigned int lane = threadIdx.x & 63;
+  const unsigned int idx = 64u * row + lane;
+  const uint32_t x = idx < live ? T.cw[cur][idx] : 0u;
+  uint32_t acc0 = 0xffffffffu, acc1 = 0xffffffffu;
+  const uint4 *sp = reinterpret_cast<const uint4 *>(&T.seg[buf][64 * chunk]);
 #pragma unroll
-  for (int r = 0; r < ROWS; ++r) {
-    const unsigned int idx = 64u * r + lane;
-    x[r] = idx < live ? T.cw[cur][idx] : 0u;
-    acc[r] = 0xffffffffu;
+  for (int i = 0; i < 16; i += 2) {
+    const uint4 c = sp[i], e = sp[i + 1];
+    acc0 = umin3(acc0, dist(x, c.x), dist(x, c.y));
+    acc1 = umin3(acc1, dist(x, c.z), dist(x, c.w));
+    acc0 = umin3(acc0, dist(x, e.x), dist(x, e.y));
+    acc1 = umin3(acc1, dist(x, e.z), dist(x, e.w));
   }
-  const uint4 *sp = reinterpret_cast<const uint4 *>(&T.seg[buf][64 * wave]);
-#pragma unroll 4
-  for (int i = 0; i < 16; ++i) {
-    const uint4 c = sp[i];
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-      acc[r] = umin3(acc[r], dist(x[r], c.x), dist(x[r], c.y));
-      acc[r] = umin3(acc[r], dist(x[r], c.z), dist(x[r], c.w));
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < kRows; ++r) m[r] = 0;
-#pragma unroll
-  for (int r = 0; r < ROWS; ++r) m[r] = ballot(acc[r] < d && 64u * r + lane < live);
+  return ballot(umin(acc0, acc1) < d && idx < live);
+}
+
+// Segment length (words, a multiple of 64) staged for `live` candidates: the
+// fewer live candidates, the longer the segment, so that a segment is about
+// one 64x64 block per wave whatever the live count.
+__device__ __forceinline__ unsigned int seg_len_for(unsigned int live) {
+  const unsigned int rows = (live + 63) / 64;
+  unsigned int p2 = 1;
+  while (p2 < rows) p2 <<= 1;
+  const unsigned int chunks = (unsigned int)kWaves / p2;
+  return 64u * (chunks ? chunks : 1u);
 }
 
 // Screen candidates id0 .. id0+nc-1 of `src` (nc <= kTile) against
-// code[a, b), newest segment first, with the whole workgroup: each wave takes
-// 64 words of a 1024-word segment staged in LDS (the next segment is
-// prefetched into registers meanwhile).  After every segment the conflicts of
-// all waves are merged, killed candidates are marked in `src`, candidates
-// killed elsewhere are dropped, and the survivors are compacted, so the work
-// per segment follows the live count and the loop stops when none is left.
-// Returns the executed checks (candidate slots x words).
+// code[a, b), newest segment first, with the whole workgroup.  The segment
+// (64..1024 words, longer as fewer candidates stay live) is staged in LDS and
+// the next one is prefetched into registers meanwhile; the waves split the
+// (row of 64 candidates) x (chunk of 64 words) blocks.  After every segment
+// the conflicts are merged, killed candidates are marked in `src`, and the
+// survivors are compacted; the loop stops when none is left.  Every other
+// segment each live candidate is also looked up in `src` (overlapped with the
+// compute) to drop the ones another workgroup killed.  Returns the executed
+// checks (candidate slots x words).
 __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint32_t *code, uint32_t id0,
                                           uint32_t nc, unsigned long long a, unsigned long long b,
                                           uint32_t d) {
@@ -426,32 +456,35 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
   int cur = 0, buf = 0;
   unsigned long long checks = 0;
   unsigned long long hi = b;
+  unsigned int nseg = 0;
+  unsigned int slen = seg_len_for(live);
   uint32_t nxt = 0;
   if (live > 0 && hi > a) {
-    const unsigned long long lo_s = hi > a + kSeg ? hi - kSeg : a;
+    const unsigned long long lo_s = hi > a + slen ? hi - slen : a;
     const unsigned long long idx = lo_s + tid;
     nxt = code[idx < hi ? idx : hi - 1];
   }
   while (live > 0 && hi > a) {
-    const unsigned long long lo_s = hi > a + kSeg ? hi - kSeg : a;
-    T.seg[buf][tid] = nxt;
+    const unsigned long long lo_s = hi > a + slen ? hi - slen : a;
+    if (tid < (int)slen) T.seg[buf][tid] = nxt;  // short segments repeat the oldest word
     __syncthreads();
+    const unsigned int next_len = seg_len_for(live);
     if (lo_s > a) {  // prefetch the next (older) segment
-      const unsigned long long lo2 = lo_s > a + kSeg ? lo_s - kSeg : a;
+      const unsigned long long lo2 = lo_s > a + next_len ? lo_s - next_len : a;
       const unsigned long long idx = lo2 + tid;
       nxt = code[idx < lo_s ? idx : lo_s - 1];
     }
-    unsigned long long m[kRows];
-    const unsigned int rows = (live + 63) / 64;
-    if (rows == 1) segment_rows<1>(T, cur, buf, live, d, m);
-    else if (rows == 2) segment_rows<2>(T, cur, buf, live, d, m);
-    else if (rows == 3) segment_rows<3>(T, cur, buf, live, d, m);
-    else segment_rows<4>(T, cur, buf, live, d, m);
-    if (lane == 0) {
-#pragma unroll
-      for (int r = 0; r < kRows; ++r) T.killw[wave][r] = m[r];
+    const bool recheck = (nseg & 1) != 0;
+    uint32_t deadw = 0;
+    if (recheck && tid < (int)live) deadw = src.dead_word(T.ci[cur][tid]);
+    const unsigned int rows = (live + 63) / 64, chunks = slen / 64;
+    if (lane < kRows) T.killw[wave][lane] = 0;
+    for (unsigned int blk = wave; blk < rows * chunks; blk += kWaves) {
+      const unsigned int row = blk % rows, chunk = blk / rows;
+      const unsigned long long k = row_chunk(T, cur, buf, row, chunk, live, d);
+      if (lane == 0) T.killw[wave][row] |= k;  // this wave's own slot
     }
-    checks += 64ull * rows * kSeg;
+    checks += 64ull * rows * slen;
     __syncthreads();
     keep = false;
     if (tid < (int)live) {
@@ -462,71 +495,75 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
       word = T.cw[cur][tid];
       id = T.ci[cur][tid];
       if (killed) src.kill(id);
-      keep = !killed && !src.is_dead(id);
+      keep = !killed && !(recheck && ((deadw >> (id & 31)) & 1));
     }
     live = tile_compact(T, cur ^ 1, keep, word, id);
     cur ^= 1;
     buf ^= 1;
     hi = lo_s;
+    slen = next_len;
+    ++nseg;
   }
   return checks;
 }
 
-// Split of a 2-D screen (tiles x code range of `len` words) into items for
-// the grid: enough range parts to give every workgroup an item, each part a
-// whole number of segments.
+// Split of a 2-D screen (candidate tiles x a code range of `len` words) into
+// items for a team: enough range parts to give every workgroup an item, each
+// part a whole number of 1024-word segments.
 struct Split {
   unsigned long long tiles, parts, plen;
 };
 
-__device__ __forceinline__ Split make_split(unsigned long long ncand, unsigned long long len) {
+__device__ __forceinline__ Split make_split(unsigned long long ncand, unsigned long long len,
+                                            unsigned int team_size) {
   Split sp;
   sp.tiles = (ncand + kTile - 1) / kTile;
-  unsigned long long parts = (gridDim.x + sp.tiles - 1) / sp.tiles;
-  const unsigned long long maxparts = (len + kSeg - 1) / kSeg;
+  unsigned long long parts = (team_size + sp.tiles - 1) / sp.tiles;
+  const unsigned long long maxparts = (len + kSegMax - 1) / kSegMax;
   if (parts > maxparts) parts = maxparts;
   if (parts < 1) parts = 1;
-  sp.plen = ((len + parts - 1) / parts + kSeg - 1) / kSeg * kSeg;
+  sp.plen = ((len + parts - 1) / parts + kSegMax - 1) / kSegMax * kSegMax;
   sp.parts = (len + sp.plen - 1) / sp.plen;
   return sp;
 }
 
 // ---------------------------------------------------------------------------
-// Phase D: in-window resolve on workgroup 0
+// Phase D: in-window resolve (team rank 0)
 // ---------------------------------------------------------------------------
 
-__device__ void resolve_window(const Params &P, Lds &L) {
+__device__ void resolve_window(Lds &L, const TeamWs &W) {
   const int tid = threadIdx.x;
   const unsigned int s = L.s;
   const int nb = (int)((s + 63) / 64);
   const int nadj = 64 * nb * (nb + 1) / 2;
-
   ResolveLds &R = L.u.r;
+  Ctl *ctl = W.ctl;
+
   if (L.round == 0) {
     for (unsigned int j = tid; j < s; j += kBlock) L.st[j] = L.lo == 0 ? ST_PASS : ST_UNKNOWN;
-    if (P.mode == MODE_DEEP_ALL && L.lo > 0 && s > 0) {
+    if (L.mode == MODE_DEEP_ALL && L.lo > 0 && s > 0) {
       // Scan every survivor once; the resolve after that round has every fact.
       for (unsigned int k = tid; k < s; k += kBlock) {
-        P.deep_word[k] = L.s1w[k];
-        P.deep_idx[k] = k;
+        W.deep_word[k] = L.s1w[k];
+        W.deep_idx[k] = k;
       }
-      for (unsigned int k = tid; k < (s + 31) / 32; k += kBlock) P.deep_fail[k] = 0;
+      for (unsigned int k = tid; k < (s + 31) / 32; k += kBlock) W.deep_fail[k] = 0;
       if (tid == 0) {
         L.ndeep = s;
-        P.ctl->ndeep = s;
-        P.ctl->action = ACT_DEEP;
-        P.ctl->stat_rounds += 1;
+        ctl->ndeep = s;
+        ctl->action = ACT_DEEP;
+        ctl->stat_rounds += 1;
       }
       __syncthreads();
       return;
     }
   } else {
     for (unsigned int k = tid; k < L.ndeep; k += kBlock) {
-      uint32_t word = ld_relaxed(&P.deep_fail[k >> 5]);
-      L.st[P.deep_idx[k]] = (word >> (k & 31)) & 1 ? ST_FAIL : ST_PASS;
+      const uint32_t word = ld_relaxed(&W.deep_fail[k >> 5]);
+      L.st[W.deep_idx[k]] = (word >> (k & 31)) & 1 ? ST_FAIL : ST_PASS;
     }
   }
-  for (int i = tid; i < nadj; i += kBlock) R.adj[i] = P.adj[i];
+  for (int i = tid; i < nadj; i += kBlock) R.adj[i] = W.adj[i];
   __syncthreads();
 
   if (tid < 64) {
@@ -554,8 +591,8 @@ __device__ void resolve_window(const Params &P, Lds &L) {
       if (mine) R.tlist[tcount + __builtin_popcountll(acc & lanemask_lt())] = L.s1w[j];
       if (mine && st == ST_UNKNOWN) {
         const unsigned int k = ndeep + __builtin_popcountll(need & lanemask_lt());
-        P.deep_word[k] = L.s1w[j];
-        P.deep_idx[k] = j;
+        W.deep_word[k] = L.s1w[j];
+        W.deep_idx[k] = j;
       }
       tcount += __builtin_popcountll(acc);
       ndeep += __builtin_popcountll(need);
@@ -569,11 +606,11 @@ __device__ void resolve_window(const Params &P, Lds &L) {
 
   const unsigned int tcount = L.tcount, ndeep = L.ndeep;
   if (ndeep > 0) {
-    for (unsigned int k = tid; k < (ndeep + 31) / 32; k += kBlock) P.deep_fail[k] = 0;
+    for (unsigned int k = tid; k < (ndeep + 31) / 32; k += kBlock) W.deep_fail[k] = 0;
     if (tid == 0) {
-      P.ctl->ndeep = ndeep;
-      P.ctl->action = ACT_DEEP;
-      P.ctl->stat_rounds += 1;
+      ctl->ndeep = ndeep;
+      ctl->action = ACT_DEEP;
+      ctl->stat_rounds += 1;
     }
     __syncthreads();
     return;
@@ -581,9 +618,9 @@ __device__ void resolve_window(const Params &P, Lds &L) {
 
   // Commit: every tentatively accepted survivor is known to pass.
   const unsigned long long m0 = L.m0;
-  unsigned long long room = P.capacity > m0 ? P.capacity - m0 : 0;
+  const unsigned long long room = L.capacity > m0 ? L.capacity - m0 : 0;
   const unsigned int nput = tcount < room ? tcount : (unsigned int)room;
-  for (unsigned int k = tid; k < nput; k += kBlock) P.code[m0 + k] = R.tlist[k];
+  for (unsigned int k = tid; k < nput; k += kBlock) L.code[m0 + k] = R.tlist[k];
 
   // Next window length: aim for `target` survivors from this window's density.
   const unsigned long long nwin = L.pe - L.p0;
@@ -593,16 +630,15 @@ __device__ void resolve_window(const Params &P, Lds &L) {
   } else if (L.s_tot == 0) {
     next = 2 * L.w;
   } else {
-    next = L.w * P.target / L.s_tot;
+    next = L.w * L.target / L.s_tot;
     if (next > 2 * L.w) next = 2 * L.w;
   }
   if (next < kWMin) next = kWMin;
   if (next > kWMax) next = kWMax;
   next = (next + 63) & ~63ull;
-  for (unsigned long long k = tid; k < (next + 31) / 32; k += kBlock) P.win_dead[k] = 0;
+  for (unsigned long long k = tid; k < (next + 31) / 32; k += kBlock) W.win_dead[k] = 0;
 
   if (tid == 0) {
-    Ctl *ctl = P.ctl;
     ctl->stat_windows += 1;
     ctl->stat_surv += L.s;
     if (nput < tcount) {
@@ -620,111 +656,124 @@ __device__ void resolve_window(const Params &P, Lds &L) {
 }
 
 // ---------------------------------------------------------------------------
-// The persistent kernel
+// Building one code with the team
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(kBlock) greedy_kernel(Params P) {
-  __shared__ Lds L;
+__device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
   const int tid = threadIdx.x;
   const unsigned int lane = tid & 63;
-  const unsigned long long gwave = (unsigned long long)blockIdx.x * kWaves + (tid >> 6);
-  const unsigned long long nwaves = (unsigned long long)gridDim.x * kWaves;
-  const uint32_t d = (uint32_t)P.d;
-  unsigned long long my_near = 0, my_deep = 0, my_pairs = 0;
-
-  init_tables(L.tab, P.n);
-  barrier_join(L, P.bar, P.ctl, P.spin_limit);
+  const uint32_t d = (uint32_t)L.d;
+  const unsigned long long tw = (unsigned long long)L.team_rank * kWaves + (tid >> 6);
+  const unsigned long long tnw = (unsigned long long)L.team_size * kWaves;
+  Ctl *ctl = W.ctl;
+  // Phase clock (team rank 0 only): time from the end of one team barrier to
+  // the end of the next is charged to the phase in between.
+  const bool timer = L.team_rank == 0 && tid == 0;
+  unsigned long long tk = timer ? wall_clock64() : 0;
+  auto charge = [&](int phase) {
+    if (timer) {
+      const unsigned long long now = wall_clock64();
+      ctl->ticks[phase] += now - tk;
+      tk = now;
+    }
+  };
 
   for (;;) {
     if (tid == 0) {
-      L.p0 = ld_relaxed(&P.ctl->p);
-      L.m0 = ld_relaxed(&P.ctl->m);
-      L.w = ld_relaxed(&P.ctl->w);
-      L.status = ld_relaxed(&P.ctl->status);
+      L.p0 = ld_relaxed(&ctl->p);
+      L.m0 = ld_relaxed(&ctl->m);
+      L.w = ld_relaxed(&ctl->w);
+      L.status = ld_relaxed(&ctl->status);
       L.round = 0;
     }
     __syncthreads();
-    if (L.status != 0 || L.p0 >= P.total) break;
+    if (L.status != 0 || L.abort || L.p0 >= L.total) break;
     const unsigned long long p0 = L.p0, m0 = L.m0;
-    const unsigned long long pe0 = p0 + L.w < P.total ? p0 + L.w : P.total;
+    const unsigned long long pe0 = p0 + L.w < L.total ? p0 + L.w : L.total;
     const unsigned long long nwin = pe0 - p0;
-    const unsigned long long lo = m0 > P.near_depth ? m0 - P.near_depth : 0;
+    const unsigned long long lo = m0 > L.near_depth ? m0 - L.near_depth : 0;
     if (tid == 0) L.lo = lo;
 
     // ---- A: near screen of [p0, pe0) against code[lo, m0) -----------------
     if (m0 > lo) {
-      const Split sp = make_split(nwin, m0 - lo);
-      const Source src{&L.tab, P.n, P.ord, p0, nullptr, P.win_dead};
-      for (unsigned long long it = blockIdx.x; it < sp.tiles * sp.parts; it += gridDim.x) {
+      const Split sp = make_split(nwin, m0 - lo, L.team_size);
+      const Source src{&L.tab, L.n, L.ord, p0, nullptr, W.win_dead};
+      for (unsigned long long it = L.team_rank; it < sp.tiles * sp.parts; it += L.team_size) {
         const unsigned long long part = it / sp.tiles, tile = it % sp.tiles;
         const unsigned long long b = m0 - part * sp.plen;
         const unsigned long long a = b > lo + sp.plen ? b - sp.plen : lo;
         const unsigned long long id0 = tile * kTile;
         const uint32_t nc = (uint32_t)(nwin - id0 < (unsigned long long)kTile ? nwin - id0 : kTile);
-        my_near += tile_screen(L, src, P.code, (uint32_t)id0, nc, a, b, d);
+        const unsigned long long c = tile_screen(L, src, L.code, (uint32_t)id0, nc, a, b, d);
+        if (tid == 0) L.cnt_near += c;
       }
     }
-    grid_barrier(L, P.bar, P.ctl, P.spin_limit);
+    team_barrier(L, P, P.spin_limit);
+    charge(0);
 
     // ---- C: survivor list (every workgroup) and in-window pairs ------------
     {
       if (tid == 0) {
-        L.s_tot = 0;
         L.truncated = 0;
         L.pe = pe0;
       }
       __syncthreads();
-      const unsigned long long nwords = (nwin + 31) / 32;
-      for (unsigned long long w0 = 0; w0 < nwords; w0 += kBlock) {
-        const unsigned long long wi = w0 + tid;
-        uint32_t liveb = 0;
-        if (wi < nwords) {
-          const uint32_t dead = ld_relaxed(&P.win_dead[wi]);
-          const unsigned long long rem = nwin - wi * 32;
-          const uint32_t valid = rem >= 32 ? 0xffffffffu : ((1u << rem) - 1u);
-          liveb = ~dead & valid;
-        }
-        // workgroup exclusive scan of popcounts
-        const unsigned int cnt = __builtin_popcount(liveb);
-        unsigned int incl = cnt;
+      // Each thread owns a contiguous run of up to kWordsPerThread mask words
+      // (all loaded at once), so survivors come out in position order.
+      const unsigned int nwords = (unsigned int)((nwin + 31) / 32);
+      const unsigned int per = (nwords + kBlock - 1) / kBlock;
+      uint32_t liveb[kWordsPerThread];
+      unsigned int cnt = 0;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-          const unsigned int y = __shfl_up(incl, off);
-          if ((int)lane >= off) incl += y;
+      for (int k = 0; k < kWordsPerThread; ++k) {
+        const unsigned int wi = tid * per + k;
+        liveb[k] = 0;
+        if (k < (int)per && wi < nwords) {
+          const uint32_t dead = ld_relaxed(&W.win_dead[wi]);
+          const unsigned long long rem = nwin - 32ull * wi;
+          const uint32_t valid = rem >= 32 ? 0xffffffffu : ((1u << rem) - 1u);
+          liveb[k] = ~dead & valid;
         }
-        if (lane == 63) L.wsum[tid >> 6] = incl;
-        __syncthreads();
-        unsigned int before = L.s_tot;
-        for (int wv = 0; wv < (tid >> 6); ++wv) before += L.wsum[wv];
-        unsigned int idx = before + incl - cnt;
-        while (liveb) {
-          const int bpos = __builtin_ctz(liveb);
-          liveb &= liveb - 1;
-          const unsigned long long off = wi * 32 + bpos;
+        cnt += __builtin_popcount(liveb[k]);
+      }
+      unsigned int incl = cnt;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const unsigned int y = __shfl_up(incl, off);
+        if ((int)lane >= off) incl += y;
+      }
+      if (lane == 63) L.wsum[tid >> 6] = incl;
+      __syncthreads();
+      unsigned int idx = incl - cnt;
+      for (int wv = 0; wv < (tid >> 6); ++wv) idx += L.wsum[wv];
+#pragma unroll
+      for (int k = 0; k < kWordsPerThread; ++k) {
+        uint32_t bits = liveb[k];
+        while (bits) {
+          const int bpos = __builtin_ctz(bits);
+          bits &= bits - 1;
+          const unsigned long long off = 32ull * (tid * per + k) + bpos;
           if (idx < (unsigned int)kSMax) {
-            L.s1w[idx] = position_word(L.tab, P.n, P.ord, p0 + off);
+            L.s1w[idx] = position_word(L.tab, L.n, L.ord, p0 + off);
           } else if (idx == (unsigned int)kSMax) {
             L.pe = p0 + off;  // the window ends before the first survivor that does not fit
             L.truncated = 1;
           }
           ++idx;
         }
-        __syncthreads();
-        if (tid == 0) {
-          unsigned int tot = 0;
-          for (int wv = 0; wv < kWaves; ++wv) tot += L.wsum[wv];
-          L.s_tot += tot;
-        }
-        __syncthreads();
-        if (L.truncated) break;
       }
-      if (tid == 0) L.s = L.s_tot < (unsigned int)kSMax ? L.s_tot : (unsigned int)kSMax;
+      if (tid == 0) {
+        unsigned int tot = 0;
+        for (int wv = 0; wv < kWaves; ++wv) tot += L.wsum[wv];
+        L.s_tot = tot;
+        L.s = tot < (unsigned int)kSMax ? tot : (unsigned int)kSMax;
+      }
       __syncthreads();
 
       const unsigned int s = L.s;
       const unsigned int nb = (s + 63) / 64;
       const unsigned int ntiles = nb * (nb + 1) / 2;
-      for (unsigned long long t = gwave; t < ntiles; t += nwaves) {
+      for (unsigned long long t = tw; t < ntiles; t += tnw) {
         unsigned int I = 0;
         while ((I + 1) * (I + 2) / 2 <= t) ++I;
         const unsigned int J = (unsigned int)t - I * (I + 1) / 2;
@@ -737,81 +786,206 @@ __global__ void __launch_bounds__(kBlock) greedy_kernel(Params P) {
           if (c < cmax && dist(xj, y) < d) mask |= 1ull << c;
         }
         if (j >= s) mask = 0;
-        P.adj[64 * (I * (I + 1) / 2) + 64 * J + lane] = mask;
-        my_pairs += 64 * 64;
+        W.adj[64 * (I * (I + 1) / 2) + 64 * J + lane] = mask;
+        if (lane == 0) atomicAdd(&L.cnt_pairs, 64ull * 64ull);
       }
     }
-    grid_barrier(L, P.bar, P.ctl, P.spin_limit);
+    team_barrier(L, P, P.spin_limit);
+    charge(1);
 
     // ---- D / E rounds ------------------------------------------------------
     for (;;) {
-      if (blockIdx.x == 0) resolve_window(P, L);
-      grid_barrier(L, P.bar, P.ctl, P.spin_limit);
+      if (L.team_rank == 0) resolve_window(L, W);
+      team_barrier(L, P, P.spin_limit);
+      charge(2);
       if (tid == 0) {
-        L.action = ld_relaxed(&P.ctl->action);
-        L.ndeep = ld_relaxed(&P.ctl->ndeep);
-        L.status = ld_relaxed(&P.ctl->status);
+        L.action = ld_relaxed(&ctl->action);
+        L.ndeep = ld_relaxed(&ctl->ndeep);
+        L.status = ld_relaxed(&ctl->status);
       }
       __syncthreads();
-      if (L.action != ACT_DEEP || L.status != 0) break;
+      if (L.action != ACT_DEEP || L.status != 0 || L.abort) break;
 
-      // ---- E: deep scan of the listed survivors against code[0, lo) ----------
+      // ---- E: deep scan of the listed survivors against code[0, lo) --------
       {
         const unsigned long long nd = L.ndeep;
-        const Split sp = make_split(nd, lo);
-        const Source src{&L.tab, P.n, P.ord, 0, P.deep_word, P.deep_fail};
-        for (unsigned long long it = blockIdx.x; it < sp.tiles * sp.parts; it += gridDim.x) {
+        const Split sp = make_split(nd, lo, L.team_size);
+        const Source src{&L.tab, L.n, L.ord, 0, W.deep_word, W.deep_fail};
+        for (unsigned long long it = L.team_rank; it < sp.tiles * sp.parts; it += L.team_size) {
           const unsigned long long part = it / sp.tiles, tile = it % sp.tiles;
           const unsigned long long b = lo - part * sp.plen;
           const unsigned long long a = b > sp.plen ? b - sp.plen : 0;
           const unsigned long long id0 = tile * kTile;
           const uint32_t nc = (uint32_t)(nd - id0 < (unsigned long long)kTile ? nd - id0 : kTile);
-          my_deep += tile_screen(L, src, P.code, (uint32_t)id0, nc, a, b, d);
+          const unsigned long long c = tile_screen(L, src, L.code, (uint32_t)id0, nc, a, b, d);
+          if (tid == 0) L.cnt_deep += c;
         }
       }
       if (tid == 0) L.round += 1;
-      grid_barrier(L, P.bar, P.ctl, P.spin_limit);
+      team_barrier(L, P, P.spin_limit);
+      charge(3);
     }
-    if (L.action == ACT_STOP || L.status != 0) break;
+    if (L.action == ACT_STOP || L.status != 0 || L.abort) break;
   }
-
-  if (tid == 0) {
-    __hip_atomic_fetch_add(&P.ctl->stat_near, my_near, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(&P.ctl->stat_deep, my_deep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  if (lane == 0)
-    __hip_atomic_fetch_add(&P.ctl->stat_pairs, my_pairs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (blockIdx.x == 0 && tid == 0 && P.count_out) *P.count_out = ld_relaxed(&P.ctl->m);
-}
-
-// Workspace initialisation (a kernel rather than memset, so that it can live
-// in captured graphs).
-__global__ void init_kernel(Ctl *ctl, Bar *bar, uint32_t *win_dead, unsigned long long w0) {
-  const unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
-  if (i == 0) {
-    Ctl c;
-    memset(&c, 0, sizeof(c));
-    c.w = w0;
-    *ctl = c;
-  }
-  for (unsigned long long k = i; k < sizeof(Bar) / sizeof(unsigned int);
-       k += (unsigned long long)gridDim.x * blockDim.x)
-    reinterpret_cast<unsigned int *>(bar)[k] = 0;
-  for (unsigned long long k = i; k < kWMax / 32; k += (unsigned long long)gridDim.x * blockDim.x)
-    win_dead[k] = 0;
 }
 
 // d = 1: every pair of distinct words is at distance >= 1, so the code is the
 // whole ordering.
-__global__ void emit_ordering_kernel(int n, int ord, uint32_t *code, unsigned long long count,
-                                     unsigned long long *count_out) {
-  __shared__ Tables T;
-  init_tables(T, n);
-  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
-  for (unsigned long long p = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; p < count;
-       p += stride)
-    code[p] = position_word(T, n, ord, p);
-  if (blockIdx.x == 0 && threadIdx.x == 0 && count_out) *count_out = count;
+__device__ void emit_ordering(Lds &L, const TeamWs &W) {
+  const unsigned long long count = L.total < L.capacity ? L.total : L.capacity;
+  const unsigned long long stride = (unsigned long long)L.team_size * kBlock;
+  for (unsigned long long p = (unsigned long long)L.team_rank * kBlock + threadIdx.x; p < count; p += stride)
+    L.code[p] = position_word(L.tab, L.n, L.ord, p);
+  if (L.team_rank == 0 && threadIdx.x == 0) {
+    W.ctl->m = count;
+    if (count < L.total) set_status(W.ctl, GC_ECAPACITY);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The persistent kernel: teams pull jobs until the queue is empty
+// ---------------------------------------------------------------------------
+
+// Claim the next job (team rank 0, thread 0).  Batch: a fixed count.  Server:
+// wait (bounded by idle_limit polls) until the host publishes one, or stop
+// when the host asks for shutdown.  Returns -1 when the team should stop.
+__device__ int claim_job(const Params &P) {
+  if (P.njobs_fixed >= 0) {
+    const unsigned int j =
+        __hip_atomic_fetch_add(&P.dq->claimed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return j < (unsigned int)P.njobs_fixed ? (int)j : -1;
+  }
+  unsigned int idle = 0;
+  for (;;) {
+    if (ld_relaxed(&P.dq->abort)) return -1;
+    const unsigned int sub = ld_sys(&P.hq->submitted);
+    unsigned int c = ld_relaxed(&P.dq->claimed);
+    if (c < sub) {
+      if (__hip_atomic_compare_exchange_strong(&P.dq->claimed, &c, c + 1, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        return (int)c;
+      continue;
+    }
+    if (ld_sys(&P.hq->shutdown)) return -1;
+    if (++idle > P.idle_limit) return -1;
+    __builtin_amdgcn_s_sleep(8);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) greedy_persistent(Params P) {
+  __shared__ Lds L;
+  const int tid = threadIdx.x;
+  team_join(L, P);
+  char *base = P.team_ws + (unsigned long long)L.team * P.team_ws_stride;
+  const TeamWs W = team_ws(base);
+  // The claim wait (server) may last up to idle_limit polls.
+  const unsigned int claim_limit = P.idle_limit + P.spin_limit;
+
+  while (!L.abort) {
+    if (L.team_rank == 0 && tid == 0) {
+      const int j = claim_job(P);
+      W.ctl->job = j;
+      if (j >= 0) {
+        Job *J = &P.jobs[j];
+        st_sys(&J->t_claim, (unsigned long long)wall_clock64());
+      }
+    }
+    team_barrier(L, P, claim_limit);
+    if (tid == 0) L.job = ld_relaxed(&W.ctl->job);
+    __syncthreads();
+    if (L.job < 0 || L.abort) break;
+
+    // Load the job (system-scope loads: the array may live in host memory).
+    if (tid == 0) {
+      Job *J = &P.jobs[L.job];
+      L.n = ld_sys(&J->n);
+      L.d = ld_sys(&J->d);
+      L.ord = ld_sys(&J->ord);
+      const int mode = ld_sys(&J->mode);
+      // Graded orders reject many survivors deep in the code: scanning every
+      // survivor once beats repeated tentative rounds there.
+      L.mode = mode ? mode : ((L.ord == GC_GRLEX || L.ord == GC_GREVLEX) ? MODE_DEEP_ALL : MODE_TENTATIVE);
+      const unsigned long long nd = ld_sys(&J->near_depth);
+      L.near_depth = nd ? nd : kDefaultNear;
+      const unsigned int tg = ld_sys(&J->target);
+      L.target = tg ? (tg > (unsigned int)kSMax ? (unsigned int)kSMax : (tg < 16 ? 16 : tg)) : kDefaultTarget;
+      L.code = ld_sys(&J->code);
+      L.capacity = ld_sys(&J->capacity);
+      L.total = 1ull << L.n;
+      L.cnt_near = L.cnt_deep = L.cnt_pairs = 0;
+    }
+    __syncthreads();
+    init_tables(L.tab, L.n);
+    if (L.team_rank == 0 && tid == 0) {
+      Ctl *c = W.ctl;
+      c->m = 0;
+      c->p = 0;
+      c->w = kWMin;
+      c->status = 0;
+      c->action = ACT_NEXT;
+      c->ndeep = 0;
+      c->stat_windows = c->stat_rounds = c->stat_surv = 0;
+      c->stat_near = c->stat_deep = c->stat_pairs = 0;
+      c->ticks[0] = c->ticks[1] = c->ticks[2] = c->ticks[3] = 0;
+    }
+    for (unsigned long long k = (unsigned long long)L.team_rank * kBlock + tid; k < kWMax / 32;
+         k += (unsigned long long)L.team_size * kBlock)
+      W.win_dead[k] = 0;
+    team_barrier(L, P, P.spin_limit);
+
+    if (L.d <= 1) emit_ordering(L, W);
+    else build_code(L, P, W);
+
+    __syncthreads();
+    if (tid == 0) {
+      __hip_atomic_fetch_add(&W.ctl->stat_near, L.cnt_near, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&W.ctl->stat_deep, L.cnt_deep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&W.ctl->stat_pairs, L.cnt_pairs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    team_barrier(L, P, P.spin_limit);
+    if (L.abort) break;
+
+    // Completion: outputs first, then `done` with system-scope release, so a
+    // host that sees done=1 also sees the words and the count.
+    if (L.team_rank == 0 && tid == 0) {
+      Job *J = &P.jobs[L.job];
+      Ctl *c = W.ctl;
+      const unsigned long long m = ld_relaxed(&c->m);
+      unsigned long long *cnt = ld_sys(&J->count);
+      if (cnt) *cnt = m;
+      st_sys(&J->out_count, m);
+      st_sys(&J->windows, ld_relaxed(&c->stat_windows));
+      st_sys(&J->rounds, ld_relaxed(&c->stat_rounds));
+      st_sys(&J->survivors, ld_relaxed(&c->stat_surv));
+      st_sys(&J->chk_near, ld_relaxed(&c->stat_near));
+      st_sys(&J->chk_deep, ld_relaxed(&c->stat_deep));
+      st_sys(&J->chk_pairs, ld_relaxed(&c->stat_pairs));
+      st_sys(&J->ticks_near, ld_relaxed(&c->ticks[0]));
+      st_sys(&J->ticks_surv, ld_relaxed(&c->ticks[1]));
+      st_sys(&J->ticks_resolve, ld_relaxed(&c->ticks[2]));
+      st_sys(&J->ticks_deep, ld_relaxed(&c->ticks[3]));
+      st_sys(&J->status, ld_relaxed(&c->status));
+      st_sys(&J->t_done, (unsigned long long)wall_clock64());
+      __hip_atomic_store(&J->done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_fetch_add(&P.dq->completed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// Reset of the barrier block and the device queue before a launch (a kernel
+// rather than a memset, so that it can live in captured graphs).
+__global__ void init_kernel(Bar *bar, DevQueue *dq, int reset_queue) {
+  const unsigned int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned int nbar = sizeof(Bar) / sizeof(unsigned int);
+  for (unsigned int k = i; k < nbar; k += gridDim.x * blockDim.x) reinterpret_cast<unsigned int *>(bar)[k] = 0;
+  if (i == 0) {
+    if (reset_queue) {
+      dq->claimed = 0;
+      dq->completed = 0;
+    }
+    dq->abort = 0;
+    dq->launches += 1;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -830,24 +1004,21 @@ int fail(int code, const char *fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                                      \
-  do {                                                                                     \
-    hipError_t e_ = (expr);                                                                \
-    if (e_ != hipSuccess)                                                                  \
+#define HIP_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
       return fail(GC_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
-                  __LINE__);                                                               \
+                  __LINE__);                                                                   \
   } while (0)
 
 struct DeviceInfo {
-  int cus = 0;
-  int coop = 0;
-  int max_blocks_per_cu = 0;
+  int cus = 0, coop = 0, blocks_per_cu = 0;
 };
-
 std::mutex g_info_mu;
 DeviceInfo g_info[64];
 
-int device_info(int dev, DeviceInfo *out) {
+int device_info(int dev, int *cus, int *coop, int *blocks_per_cu) {
   std::lock_guard<std::mutex> lk(g_info_mu);
   if (dev < 0 || dev >= 64) return fail(GC_EDEVICE, "device ordinal %d out of range", dev);
   DeviceInfo &di = g_info[dev];
@@ -855,11 +1026,25 @@ int device_info(int dev, DeviceInfo *out) {
     HIP_TRY(hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev));
     HIP_TRY(hipDeviceGetAttribute(&di.coop, hipDeviceAttributeCooperativeLaunch, dev));
     int nb = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, greedy_kernel, kBlock, 0));
-    di.max_blocks_per_cu = nb;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, greedy_persistent, kBlock, 0));
+    di.blocks_per_cu = nb;
   }
-  *out = di;
+  *cus = di.cus;
+  *coop = di.coop;
+  *blocks_per_cu = di.blocks_per_cu;
   return GC_OK;
+}
+
+hipError_t launch_init(Bar *bar, DevQueue *dq, int reset_queue, hipStream_t stream) {
+  hipLaunchKernelGGL(init_kernel, dim3(4), dim3(256), 0, stream, bar, dq, reset_queue);
+  return hipGetLastError();
+}
+
+hipError_t launch_persistent(const Params &P, unsigned int grid, hipStream_t stream) {
+  Params copy = P;
+  void *args[] = {&copy};
+  return hipLaunchCooperativeKernel((const void *)greedy_persistent, dim3(grid), dim3(kBlock), args, 0,
+                                    stream);
 }
 
 unsigned long long binom_host(int a, int b) {
@@ -867,6 +1052,113 @@ unsigned long long binom_host(int a, int b) {
   unsigned long long c = 1;
   for (int t = 1; t <= b; ++t) c = c * (unsigned long long)(a - b + t) / (unsigned long long)t;
   return c;
+}
+
+int check_job_args(int n, int d, int ordering) {
+  if (n < 1 || n > 32) return fail(GC_EINVAL, "n=%d outside [1, 32]", n);
+  if (d < 1) return fail(GC_EINVAL, "d=%d must be >= 1", d);
+  if (ordering < GC_LEX || ordering > GC_GREVLEX) return fail(GC_EINVAL, "unknown ordering %d", ordering);
+  return GC_OK;
+}
+
+// Grid for a launch: one workgroup per compute unit unless asked otherwise.
+int pick_grid(unsigned int requested, unsigned int *grid) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  int cus = 0, coop = 0, bpc = 0;
+  int rc = device_info(dev, &cus, &coop, &bpc);
+  if (rc) return rc;
+  if (!coop) return fail(GC_EDEVICE, "device %d does not support cooperative launch", dev);
+  if (bpc < 1) return fail(GC_EDEVICE, "persistent kernel does not fit on a compute unit");
+  const unsigned int g = requested ? requested : (unsigned int)cus;
+  if (g > (unsigned int)(cus * bpc))
+    return fail(GC_EINVAL, "grid_blocks %u exceeds the co-resident limit %d", g, cus * bpc);
+  *grid = g;
+  return GC_OK;
+}
+
+unsigned int spin_limit_from_env() {
+  unsigned int s = kDefaultSpin;
+  if (const char *env = getenv("GC_SPIN_LIMIT")) s = (unsigned int)strtoul(env, nullptr, 0);
+  return s;
+}
+
+// Run a batch of jobs on `stream` with `nteams` teams and wait for it.  Jobs
+// are copied to device memory and their outputs copied back into `jobs`.
+int run_batch(Job *jobs, int njobs, int nteams, unsigned int grid_req, hipStream_t stream,
+              float *kernel_ms) {
+  if (njobs <= 0) return GC_OK;
+  if (nteams != 1 && nteams != 2 && nteams != 4 && nteams != 8)
+    return fail(GC_EINVAL, "teams must be 1, 2, 4 or 8 (got %d)", nteams);
+  unsigned int grid = 0;
+  int rc = pick_grid(grid_req, &grid);
+  if (rc) return rc;
+  const size_t off_bar = 0;
+  const size_t off_dq = align256(sizeof(Bar));
+  const size_t off_jobs = off_dq + align256(sizeof(DevQueue));
+  const size_t off_ws = off_jobs + align256(sizeof(Job) * (size_t)njobs);
+  const size_t bytes = off_ws + kTeamWsBytes * (size_t)nteams;
+  char *ws = nullptr;
+  HIP_TRY(hipMallocAsync((void **)&ws, bytes, stream));
+  Params P;
+  memset(&P, 0, sizeof(P));
+  P.jobs = reinterpret_cast<Job *>(ws + off_jobs);
+  P.hq = nullptr;
+  P.dq = reinterpret_cast<DevQueue *>(ws + off_dq);
+  P.bar = reinterpret_cast<Bar *>(ws + off_bar);
+  P.njobs_fixed = njobs;
+  P.nteams = nteams;
+  P.spin_limit = spin_limit_from_env();
+  P.idle_limit = 0;
+  P.team_ws = ws + off_ws;
+  P.team_ws_stride = kTeamWsBytes;
+
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipError_t e = hipEventCreate(&ev0);
+  if (e == hipSuccess) e = hipEventCreate(&ev1);
+  if (e == hipSuccess) e = hipMemcpyAsync(P.jobs, jobs, sizeof(Job) * njobs, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = launch_init(P.bar, P.dq, 1, stream);
+  if (e == hipSuccess) e = hipEventRecord(ev0, stream);
+  if (e == hipSuccess) e = launch_persistent(P, grid, stream);
+  if (e == hipSuccess) e = hipEventRecord(ev1, stream);
+  DevQueue dq;
+  memset(&dq, 0, sizeof(dq));
+  if (e == hipSuccess) e = hipMemcpyAsync(jobs, P.jobs, sizeof(Job) * njobs, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&dq, P.dq, sizeof(dq), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e == hipSuccess && kernel_ms) e = hipEventElapsedTime(kernel_ms, ev0, ev1);
+  const hipError_t ef = hipFreeAsync(ws, stream);
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (e != hipSuccess) return fail(GC_EDEVICE, "persistent kernel failed: %s", hipGetErrorString(e));
+  if (ef != hipSuccess) return fail(GC_EDEVICE, "hipFreeAsync failed: %s", hipGetErrorString(ef));
+  if (dq.abort) return fail(GC_ETIMEOUT, "a bounded device-side wait expired");
+  return GC_OK;
+}
+
+void fill_job(Job *J, int n, int d, int ordering, uint32_t *words, uint64_t capacity, uint64_t *count,
+              const gc_tuning *tuning) {
+  memset(J, 0, sizeof(*J));
+  J->n = n;
+  J->d = d;
+  J->ord = ordering;
+  J->code = words;
+  J->capacity = capacity;
+  J->count = reinterpret_cast<unsigned long long *>(count);
+  if (tuning) {
+    J->near_depth = tuning->near_depth;
+    J->target = tuning->target_survivors;
+    J->mode = (int)tuning->resolve_mode;
+  }
+}
+
+int job_result(const Job &J, uint64_t capacity) {
+  if (!J.done) return fail(GC_ETIMEOUT, "job did not complete");
+  if (J.status == GC_ECAPACITY)
+    return fail(GC_ECAPACITY, "code exceeds capacity %llu", (unsigned long long)capacity);
+  if (J.status == GC_ETIMEOUT) return fail(GC_ETIMEOUT, "device barrier wait expired");
+  if (J.status != 0) return fail(GC_EDEVICE, "device status %d", J.status);
+  return GC_OK;
 }
 
 }  // namespace gcimpl
@@ -898,140 +1190,39 @@ int greedy_code_device_ex(int n, int d, int ordering, uint32_t *d_words, uint64_
                           uint64_t *d_count, void *hip_stream, const gc_tuning *tuning,
                           gc_stats *stats) {
   g_error.clear();
-  if (n < 1 || n > 32) return fail(GC_EINVAL, "n=%d outside [1, 32]", n);
-  if (d < 1) return fail(GC_EINVAL, "d=%d must be >= 1", d);
-  if (ordering < GC_LEX || ordering > GC_GREVLEX) return fail(GC_EINVAL, "unknown ordering %d", ordering);
+  int rc = check_job_args(n, d, ordering);
+  if (rc) return rc;
   if (!d_count) return fail(GC_EINVAL, "d_count is NULL");
   if (!d_words && capacity > 0) return fail(GC_EINVAL, "d_words is NULL");
   if (((uintptr_t)d_words & 15u) != 0) return fail(GC_EINVAL, "d_words must be 16-byte aligned");
   if (capacity == 0) return fail(GC_ECAPACITY, "capacity 0 cannot hold the zero word");
-  hipStream_t stream = (hipStream_t)hip_stream;
+  if (tuning && tuning->resolve_mode > 2) return fail(GC_EINVAL, "resolve_mode %u unknown", tuning->resolve_mode);
   if (stats) memset(stats, 0, sizeof(*stats));
-
-  int dev = 0;
-  HIP_TRY(hipGetDevice(&dev));
-  DeviceInfo di;
-  int rc = device_info(dev, &di);
+  Job J;
+  fill_job(&J, n, d, ordering, d_words, capacity, d_count, tuning);
+  float ms = 0.f;
+  rc = run_batch(&J, 1, 1, tuning ? tuning->grid_blocks : 0, (hipStream_t)hip_stream, &ms);
   if (rc) return rc;
-
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  HIP_TRY(hipEventCreate(&ev0));
-  HIP_TRY(hipEventCreate(&ev1));
-  const unsigned long long total = 1ull << n;
-
-  if (d == 1) {
-    const unsigned long long count = total < capacity ? total : capacity;
-    HIP_TRY(hipEventRecord(ev0, stream));
-    unsigned long long blocks = (count + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(emit_ordering_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, n,
-                       ordering, d_words, count, (unsigned long long *)d_count);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipEventRecord(ev1, stream));
-    HIP_TRY(hipEventSynchronize(ev1));
-    if (stats) {
-      stats->count = count;
-      HIP_TRY(hipEventElapsedTime(&stats->kernel_ms, ev0, ev1));
-    }
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
-    if (count < total) return fail(GC_ECAPACITY, "code has %llu words, capacity %llu", total, capacity);
-    return GC_OK;
-  }
-
-  if (!di.coop) return fail(GC_EDEVICE, "device %d does not support cooperative launch", dev);
-  if (di.max_blocks_per_cu < 1) return fail(GC_EDEVICE, "kernel does not fit on a compute unit");
-  unsigned int grid = (unsigned int)di.cus;
-  if (tuning && tuning->grid_blocks) grid = tuning->grid_blocks;
-  if (grid > (unsigned int)(di.cus * di.max_blocks_per_cu))
-    return fail(GC_EINVAL, "grid_blocks %u exceeds co-resident limit %d", grid,
-                di.cus * di.max_blocks_per_cu);
-
-  // Workspace: control block, window dead mask, adjacency, deep lists.
-  const size_t off_ctl = 0;
-  const size_t off_bar = 512;
-  const size_t off_dead = off_bar + ((sizeof(Bar) + 255) / 256) * 256;
-  const size_t off_adj = off_dead + (kWMax / 32) * sizeof(uint32_t);
-  const size_t off_dword = off_adj + kAdjWords * sizeof(unsigned long long);
-  const size_t off_didx = off_dword + kSMax * sizeof(uint32_t);
-  const size_t off_dfail = off_didx + kSMax * sizeof(uint32_t);
-  const size_t ws_bytes = off_dfail + (kSMax / 32) * sizeof(uint32_t) + 256;
-  char *ws = nullptr;
-  HIP_TRY(hipMallocAsync((void **)&ws, ws_bytes, stream));
-
-  Params P;
-  memset(&P, 0, sizeof(P));
-  P.n = n;
-  P.d = d;
-  P.ord = ordering;
-  P.total = total;
-  P.code = d_words;
-  P.capacity = capacity;
-  P.ctl = (Ctl *)(ws + off_ctl);
-  P.bar = (Bar *)(ws + off_bar);
-  P.count_out = (unsigned long long *)d_count;
-  P.win_dead = (uint32_t *)(ws + off_dead);
-  P.adj = (unsigned long long *)(ws + off_adj);
-  P.deep_word = (uint32_t *)(ws + off_dword);
-  P.deep_idx = (uint32_t *)(ws + off_didx);
-  P.deep_fail = (uint32_t *)(ws + off_dfail);
-  P.near_depth = (tuning && tuning->near_depth) ? tuning->near_depth : kDefaultNear;
-  P.target = (tuning && tuning->target_survivors) ? tuning->target_survivors : kDefaultTarget;
-  if (P.target > (unsigned int)kSMax) P.target = kSMax;
-  if (P.target < 16) P.target = 16;
-  P.spin_limit = kDefaultSpin;
-  // Resolve mode: graded orders reject many survivors deep in the code, so
-  // scanning every survivor once beats repeated tentative rounds there.
-  P.mode = (ordering == GC_GRLEX || ordering == GC_GREVLEX) ? MODE_DEEP_ALL : MODE_TENTATIVE;
-  if (tuning && tuning->resolve_mode) P.mode = tuning->resolve_mode == 2 ? MODE_DEEP_ALL : MODE_TENTATIVE;
-  if (const char *env = getenv("GC_SPIN_LIMIT")) P.spin_limit = (unsigned int)strtoul(env, nullptr, 0);
-
-  int status = GC_OK;
-  hipLaunchKernelGGL(init_kernel, dim3(8), dim3(256), 0, stream, P.ctl, P.bar, P.win_dead,
-                     (unsigned long long)kWMin);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = hipEventRecord(ev0, stream);
-  if (e == hipSuccess) {
-    void *args[] = {&P};
-    e = hipLaunchCooperativeKernel((const void *)greedy_kernel, dim3(grid), dim3(kBlock), args, 0,
-                                   stream);
-  }
-  if (e == hipSuccess) e = hipEventRecord(ev1, stream);
-  Ctl host_ctl;
-  memset(&host_ctl, 0, sizeof(host_ctl));
-  if (e == hipSuccess) e = hipMemcpyAsync(&host_ctl, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  hipError_t ef = hipFreeAsync(ws, stream);
-  if (e != hipSuccess) {
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
-    return fail(GC_EDEVICE, "greedy kernel failed: %s", hipGetErrorString(e));
-  }
-  if (ef != hipSuccess) return fail(GC_EDEVICE, "hipFreeAsync failed: %s", hipGetErrorString(ef));
   if (stats) {
-    stats->count = host_ctl.m;
-    stats->windows = host_ctl.stat_windows;
-    stats->resolve_rounds = host_ctl.stat_rounds;
-    stats->survivors = host_ctl.stat_surv;
-    stats->checks_near = host_ctl.stat_near;
-    stats->checks_deep = host_ctl.stat_deep;
-    stats->checks_pairs = host_ctl.stat_pairs;
-    (void)hipEventElapsedTime(&stats->kernel_ms, ev0, ev1);
+    stats->count = J.out_count;
+    stats->windows = J.windows;
+    stats->resolve_rounds = J.rounds;
+    stats->survivors = J.survivors;
+    stats->checks_near = J.chk_near;
+    stats->checks_deep = J.chk_deep;
+    stats->checks_pairs = J.chk_pairs;
+    stats->kernel_ms = ms;
+    stats->near_ms = J.ticks_near / 1e5;
+    stats->survivors_ms = J.ticks_surv / 1e5;
+    stats->resolve_ms = J.ticks_resolve / 1e5;
+    stats->deep_ms = J.ticks_deep / 1e5;
   }
-  (void)hipEventDestroy(ev0);
-  (void)hipEventDestroy(ev1);
-  status = host_ctl.status;
-  if (status == GC_ECAPACITY)
-    return fail(GC_ECAPACITY, "code exceeds capacity %llu", (unsigned long long)capacity);
-  if (status == GC_ETIMEOUT) return fail(GC_ETIMEOUT, "device barrier wait expired");
-  if (status != 0) return fail(GC_EDEVICE, "device status %d", status);
-  return GC_OK;
+  return job_result(J, capacity);
 }
 
 int greedy_code_device(int n, int d, int ordering, uint32_t *d_words, uint64_t capacity,
                        uint64_t *d_count, void *hip_stream) {
-  return greedy_code_device_ex(n, d, ordering, d_words, capacity, d_count, hip_stream, nullptr,
-                               nullptr);
+  return greedy_code_device_ex(n, d, ordering, d_words, capacity, d_count, hip_stream, nullptr, nullptr);
 }
 
 int greedy_code(int n, int d, int ordering, uint32_t *out_words, uint64_t *out_count) {
@@ -1068,6 +1259,33 @@ int greedy_code(int n, int d, int ordering, uint32_t *out_words, uint64_t *out_c
   (void)hipFree(dw);
   (void)hipFree(dc);
   return rc;
+}
+
+int greedy_code_batch(gc_job *jobs, int njobs, int teams, void *hip_stream, float *kernel_ms) {
+  g_error.clear();
+  if (njobs < 0 || (!jobs && njobs > 0)) return fail(GC_EINVAL, "bad job array");
+  if (teams == 0) teams = njobs >= 8 ? 8 : (njobs >= 4 ? 4 : (njobs >= 2 ? 2 : 1));
+  std::vector<Job> J((size_t)njobs);
+  for (int i = 0; i < njobs; ++i) {
+    gc_job &g = jobs[i];
+    int rc = check_job_args(g.n, g.d, g.ordering);
+    if (rc) return fail(GC_EINVAL, "job %d: %s", i, g_error.c_str());
+    if (!g.d_words || ((uintptr_t)g.d_words & 15u) || g.capacity == 0)
+      return fail(GC_EINVAL, "job %d: d_words must be a 16-byte aligned device array", i);
+    fill_job(&J[i], g.n, g.d, g.ordering, g.d_words, g.capacity, g.d_count, nullptr);
+  }
+  float ms = 0.f;
+  int rc = run_batch(J.data(), njobs, teams, 0, (hipStream_t)hip_stream, &ms);
+  if (kernel_ms) *kernel_ms = ms;
+  for (int i = 0; i < njobs; ++i) {
+    jobs[i].count = J[i].out_count;
+    jobs[i].status = J[i].done ? J[i].status : GC_ETIMEOUT;
+    jobs[i].device_ms = J[i].done ? (double)(J[i].t_done - J[i].t_claim) / 1e5 : 0.0;
+  }
+  if (rc) return rc;
+  for (int i = 0; i < njobs; ++i)
+    if (jobs[i].status) return fail(jobs[i].status, "job %d failed with status %d", i, jobs[i].status);
+  return GC_OK;
 }
 
 }  // extern "C"

@@ -12,6 +12,10 @@ exhaustive scan).  Instances (n, d, ordering):
 
 Usage: python tests/golden/make_expected.py [--jobs J] [--only PREFIX]
 (about an hour on 8 cores; the n=32 instances dominate).
+
+With --batch it writes tests/golden/expected_batch.txt instead: the same
+fields for each of the 256 instances of the batched workload
+(paper_1507_05398_amd.workloads.batched_instances(), seed 1507), by index.
 """
 import argparse
 import hashlib
@@ -26,6 +30,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 
 OUT = os.path.join(HERE, "expected_codes.txt")
+OUT_BATCH = os.path.join(HERE, "expected_batch.txt")
 NAMES = ["lex", "gray", "grlex", "grevlex"]
 
 
@@ -62,7 +67,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=4)
     ap.add_argument("--only", default="")
+    ap.add_argument("--batch", action="store_true")
     args = ap.parse_args()
+    if args.batch:
+        return main_batch(args.jobs)
     todo = [i for i in instances() if f"{i[0]}_{i[1]}_{i[2]}".startswith(args.only)]
     old = {}
     if os.path.exists(OUT):
@@ -77,6 +85,23 @@ def main():
             old[key] = f"{key} {m} {digest} {w_ee} {w_full}"
             print(f"{key}: |C|={m} w_ee={w_ee} w_full={w_full} ({how}, {dt:.1f}s)", flush=True)
             write(old)
+
+
+def main_batch(jobs):
+    from paper_1507_05398_amd.workloads import batched_instances  # instance list only
+    inst = batched_instances()
+    rows = {}
+    with ProcessPoolExecutor(jobs) as ex:
+        for i, (res) in enumerate(ex.map(solve, inst)):
+            (n, d, name), m, digest, w_ee, w_full, how, dt = res
+            rows[i] = f"{i} {n}_{d}_{name} {m} {digest} {w_ee} {w_full}"
+            print(f"batch {i}: {n}_{d}_{name} |C|={m} ({how}, {dt:.1f}s)", flush=True)
+    with open(OUT_BATCH + ".tmp", "w") as f:
+        f.write("# Written by tests/golden/make_expected.py --batch from the CPU oracle only.\n")
+        f.write("# index key=n_d_ordering |C| sha256(uint32 LE words) W_ee W_full\n")
+        for i in range(len(inst)):
+            f.write(rows[i] + "\n")
+    os.replace(OUT_BATCH + ".tmp", OUT_BATCH)
 
 
 def write(entries):

@@ -77,3 +77,23 @@ def test_null_and_alignment_rejected():
     assert lib.greedy_code_device(5, 3, 0, ctypes.c_void_p(68), 16, ctypes.c_void_p(64), None) == gc.GC_EINVAL
     count = ctypes.c_uint64(4)
     assert lib.greedy_code(5, 3, 0, None, ctypes.byref(count)) == gc.GC_EINVAL
+
+
+def test_batch_argument_validation_without_device():
+    lib = gc.load()
+    jobs = (gc._native.GcJob * 2)()
+    jobs[0].n, jobs[0].d, jobs[0].ordering, jobs[0].d_words, jobs[0].capacity = 5, 3, 0, 64, 16
+    jobs[1].n, jobs[1].d, jobs[1].ordering, jobs[1].d_words, jobs[1].capacity = 5, 0, 0, 64, 16
+    assert lib.greedy_code_batch(jobs, 2, 1, None, None) == gc.GC_EINVAL
+    jobs[1].d, jobs[1].d_words = 3, 68   # misaligned
+    assert lib.greedy_code_batch(jobs, 2, 1, None, None) == gc.GC_EINVAL
+    assert lib.greedy_code_batch(None, 3, 1, None, None) == gc.GC_EINVAL
+
+
+def test_server_create_fails_cleanly_without_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    h = ctypes.c_void_p()
+    assert gc.load().gc_server_create(1 << 20, 8, ctypes.byref(h)) != gc.GC_OK
+    assert gc.load().gc_server_create(1 << 20, 3, ctypes.byref(h)) == gc.GC_EINVAL

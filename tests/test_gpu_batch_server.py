@@ -1,0 +1,155 @@
+"""GPU parity of the batched launch and the job server against the oracle.
+
+Every code built in a batch or through the server must be the exact list the
+oracle produces for its (n, d, ordering); a job's result must not depend on
+what else shares the GPU with it.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1507_05398_amd as gc
+from paper_1507_05398_amd import workloads
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    gc.load()
+    return torch
+
+
+def ref(n, d, o):
+    return oracle.greedy_ball(n, d, oracle.ORDERINGS[o])[0]
+
+
+SMALL = workloads.batched_instances(seed=7, count=48, n_lo=8, n_hi=17, d_lo=2, d_hi=9)
+
+
+@pytest.mark.parametrize("teams", [1, 2, 4, 8])
+def test_batch_matches_oracle(teams):
+    log(f"[gpu] batch teams={teams} jobs={len(SMALL)}")
+    words, info, ms = gc.greedy_code_batch(SMALL, teams=teams)
+    for (n, d, o), w, inf in zip(SMALL, words, info):
+        assert inf["status"] == 0
+        assert np.array_equal(w.cpu().numpy().view(np.uint32), ref(n, d, o)), (n, d, o)
+
+
+def test_batch_with_degenerate_and_single_jobs():
+    inst = [(5, 1, "gray"), (6, 7, "lex"), (10, 10, "grevlex"), (1, 1, "lex"), (12, 3, "grlex")]
+    words, info, _ = gc.greedy_code_batch(inst, teams=8)
+    for (n, d, o), w in zip(inst, words):
+        assert np.array_equal(w.cpu().numpy().view(np.uint32), ref(n, d, o)), (n, d, o)
+    words, info, _ = gc.greedy_code_batch([(16, 4, "grlex")], teams=1)
+    assert np.array_equal(words[0].cpu().numpy().view(np.uint32), ref(16, 4, "grlex"))
+
+
+def load_expected():
+    path = os.path.join(HERE, "golden", "expected_batch.txt")
+    out = {}
+    if os.path.exists(path):
+        for line in open(path):
+            if line.strip() and not line.startswith("#"):
+                idx, key, m, digest = line.split()[:4]
+                out[int(idx)] = (key, int(m), digest)
+    return out
+
+
+def test_batched_workload_256_instances():
+    import hashlib
+    exp = load_expected()
+    inst = workloads.batched_instances()
+    assert len(exp) == len(inst), "tests/golden/expected_batch.txt is incomplete"
+    t = time.time()
+    words, info, ms = gc.greedy_code_batch(inst, teams=8)
+    log(f"[gpu] 256-instance batch: {ms:.1f} ms kernel, {time.time() - t:.1f} s wall")
+    for i, ((n, d, o), w) in enumerate(zip(inst, words)):
+        key, m, digest = exp[i]
+        assert key == f"{n}_{d}_{o}"
+        got = w.cpu().numpy().astype("<u4")
+        assert len(got) == m and hashlib.sha256(got.tobytes()).hexdigest() == digest, (i, key)
+
+
+JOBS = [(14, 3, "lex"), (16, 5, "gray"), (12, 4, "grlex"), (15, 6, "grevlex"), (18, 3, "gray"),
+        (10, 2, "lex"), (17, 8, "grlex"), (13, 7, "lex"), (20, 4, "grevlex"), (11, 3, "gray")]
+
+
+def wait_all(srv, tickets, timeout=120.0):
+    t0 = time.time()
+    pending = set(tickets)
+    while pending:
+        for t in list(pending):
+            st, _ = srv.poll(t)
+            if st in (gc.GC_JOB_DONE, gc.GC_JOB_FAILED):
+                pending.discard(t)
+        assert time.time() - t0 < timeout, "server jobs did not finish"
+        time.sleep(0.001)
+
+
+def test_server_alone_and_in_the_mix_match_oracle():
+    expected = [ref(*j) for j in JOBS]
+    with gc.Server(arena_bytes=64 << 20, teams=8) as srv:
+        # alone: one job at a time
+        for j, e in zip(JOBS, expected):
+            log(f"[gpu] server alone {j}")
+            t = srv.submit(*j)
+            wait_all(srv, [t])
+            assert np.array_equal(srv.fetch(t), e), j
+            srv.release(t)
+        # in the mix: everything at once, twice over
+        tickets = [srv.submit(*j) for j in JOBS + JOBS]
+        wait_all(srv, tickets)
+        for t, e in zip(tickets, expected + expected):
+            assert np.array_equal(srv.fetch(t), e)
+            st = srv.stats(t)
+            assert st["count"] == len(e)
+            srv.release(t)
+
+
+def test_server_admission_waits_for_memory():
+    # An arena that holds one n=16 d=3 code at a time: later jobs wait until
+    # earlier ones are released.
+    cap_bytes = gc.greedy_code_capacity(16, 3) * 4
+    jobs = [(16, 3, "lex"), (16, 3, "gray"), (16, 3, "grlex"), (16, 3, "grevlex")]
+    with gc.Server(arena_bytes=cap_bytes + 256, teams=4) as srv:
+        tickets = [srv.submit(*j) for j in jobs]
+        states = [srv.poll(t)[0] for t in tickets]
+        assert states[1:] == [gc.GC_JOB_WAITING] * 3
+        done = {}
+        t0 = time.time()
+        while len(done) < len(jobs):
+            for t, j in zip(tickets, jobs):
+                if t in done:
+                    continue
+                st, _ = srv.poll(t)
+                if st == gc.GC_JOB_DONE:
+                    done[t] = srv.fetch(t)
+                    srv.release(t)
+            assert time.time() - t0 < 120
+            time.sleep(0.001)
+        for t, j in zip(tickets, jobs):
+            assert np.array_equal(done[t], ref(*j)), j
+
+
+def test_server_relaunches_after_idle():
+    with gc.Server(arena_bytes=16 << 20, teams=2) as srv:
+        t = srv.submit(15, 3, "lex")
+        wait_all(srv, [t])
+        time.sleep(0.5)  # longer than the kernel's idle period
+        t2 = srv.submit(13, 4, "gray")
+        wait_all(srv, [t2])
+        assert np.array_equal(srv.fetch(t), ref(15, 3, "lex"))
+        assert np.array_equal(srv.fetch(t2), ref(13, 4, "gray"))
