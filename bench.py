@@ -151,7 +151,7 @@ def main():
                    "w_full_per_step": w_full},
         "roofline": {
             "bound": "alu",
-            "kernel": "greedy_kernel",
+            "kernel": "greedy_persistent",
             "achieved": round(achieved, 3),
             "peak": round(PEAK_GCHECKS, 1),
             "unit": "Gchecks/s",
