@@ -71,6 +71,140 @@ def cpu_baseline():
                       f"{checks:.3e} checks in {dt:.1f} s)"}
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def load_expected_batch():
+    path = os.path.join(ROOT, "tests", "golden", "expected_batch.txt")
+    out = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            idx, key, m, digest, w_ee, w_full = line.split()
+            out[int(idx)] = (key, int(m), digest, int(w_ee), int(w_full))
+    return out
+
+
+def digest_of(t):
+    return hashlib.sha256(t.cpu().numpy().astype("<u4").tobytes()).hexdigest()
+
+
+def bench_batched(gc, torch, steps, warmup):
+    """The 256-instance batched workload (seed 1507): one persistent launch
+    over every instance (teams by job count) against a loop of plain
+    per-instance calls on the same preallocated buffers."""
+    from paper_1507_05398_amd import workloads
+    insts = workloads.batched_instances()
+    expected = load_expected_batch()
+    plan = gc.BatchPlan(insts)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.run(stream=stream)
+    torch.cuda.synchronize()
+    walls, kms = [], []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        kms.append(plan.run(stream=stream))
+        walls.append(time.perf_counter() - t0)
+    for i, t in enumerate(plan.results()):
+        key, m, dig, _, _ = expected[i]
+        if len(t) != m or digest_of(t) != dig:
+            raise SystemExit(f"BATCH MISMATCH job {i} ({key})")
+
+    def plain():
+        for (n, d, o), (w, c) in zip(insts, plan.bufs):
+            gc.greedy_code_device(n, d, o, w, c, stream=stream)
+    for _ in range(warmup):
+        plain()
+    torch.cuda.synchronize()
+    pwalls = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        plain()
+        torch.cuda.synchronize()
+        pwalls.append(time.perf_counter() - t0)
+    for i, (w, c) in enumerate(plan.bufs):
+        key, m, dig, _, _ = expected[i]
+        if int(c.item()) != m or digest_of(w[:m]) != dig:
+            raise SystemExit(f"PLAIN MISMATCH job {i} ({key})")
+    tb, tp = sorted(walls)[len(walls) // 2], sorted(pwalls)[len(pwalls) // 2]
+    w_ee = sum(v[3] for v in expected.values())
+    return {"instances": len(insts), "seed": 1507,
+            "batched_codes_per_s": round(len(insts) / tb, 2), "batched_ms": round(tb * 1e3, 3),
+            "batched_kernel_ms": round(sorted(kms)[len(kms) // 2], 3),
+            "plain_codes_per_s": round(len(insts) / tp, 2), "plain_ms": round(tp * 1e3, 3),
+            "speedup": round(tp / tb, 3),
+            "batched_gchecks_per_s": round(w_ee / tb / 1e9, 3)}
+
+
+def bench_served(gc, torch, njobs, arena_bytes, teams, load_frac):
+    """The served workload: seeded Poisson stream of `njobs` jobs (n in
+    [10, 26] skewed small, d in [3, 10], random ordering).  Three passes: the
+    jobs one at a time through the plain host entry point (serial), all jobs
+    submitted at once to the server (its capacity), then the Poisson stream
+    at `load_frac` of that capacity.  Latency = arrival -> words in host
+    memory.  Every served result must equal the serial one."""
+    from paper_1507_05398_amd import workloads
+    unit = workloads.served_jobs(seed=1507, count=njobs, rate=1.0)
+    ref = []
+    t0 = time.perf_counter()
+    for _, n, d, o in unit:
+        ref.append(hashlib.sha256(gc.greedy_code(n, d, o).astype("<u4").tobytes()).hexdigest())
+    serial_s = time.perf_counter() - t0
+    progress(f"served: serial pass {serial_s:.2f} s")
+
+    def serve(arrivals):
+        lat = [0.0] * njobs
+        admitted_wait = 0
+        with gc.Server(arena_bytes=arena_bytes, teams=teams) as srv:
+            nxt, inflight, done = 0, {}, 0
+            t0 = time.perf_counter()
+            while done < njobs:
+                now = time.perf_counter() - t0
+                while nxt < njobs and arrivals[nxt] <= now:
+                    _, n, d, o = unit[nxt]
+                    inflight[srv.submit(n, d, o)] = nxt
+                    nxt += 1
+                progressed = False
+                for tk in list(inflight):
+                    st, _ = srv.poll(tk)
+                    if st == gc.GC_JOB_WAITING:
+                        admitted_wait += 1
+                    if st < gc.GC_JOB_DONE:
+                        continue
+                    i = inflight.pop(tk)
+                    words = srv.fetch(tk)
+                    lat[i] = time.perf_counter() - t0 - arrivals[i]
+                    srv.release(tk)
+                    if hashlib.sha256(words.astype("<u4").tobytes()).hexdigest() != ref[i]:
+                        raise SystemExit(f"SERVED MISMATCH job {i} {unit[i][1:]}")
+                    done += 1
+                    progressed = True
+                if not progressed and nxt < njobs:
+                    wait = arrivals[nxt] - (time.perf_counter() - t0)
+                    if wait > 2e-4:
+                        time.sleep(min(wait, 1e-3))
+            span = time.perf_counter() - t0
+        lat.sort()
+        return span, lat, admitted_wait
+
+    burst_span, _, _ = serve([0.0] * njobs)
+    progress(f"served: burst pass {burst_span:.2f} s")
+    capacity = njobs / burst_span
+    rate = load_frac * capacity
+    arrivals = [a / rate for a, _, _, _ in unit]
+    span, lat, waits = serve(arrivals)
+    q = lambda f: lat[min(njobs - 1, int(f * njobs))]
+    return {"jobs": njobs, "seed": 1507, "arena_bytes": arena_bytes, "teams": teams,
+            "serial_jobs_per_s": round(njobs / serial_s, 2),
+            "capacity_jobs_per_s": round(capacity, 2),
+            "offered_rate_jobs_per_s": round(rate, 2), "load_fraction": load_frac,
+            "served_jobs_per_s": round(njobs / span, 2),
+            "p50_ms": round(q(0.50) * 1e3, 3), "p99_ms": round(q(0.99) * 1e3, 3),
+            "max_ms": round(lat[-1] * 1e3, 3),
+            "polls_waiting_for_memory": waits}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +212,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=["sweep", "large"], default="sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-jobs", type=int, default=10000)
+    ap.add_argument("--served-arena-mib", type=int, default=64)
+    ap.add_argument("--served-teams", type=int, default=8)
+    ap.add_argument("--served-load", type=float, default=0.7)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -151,7 +291,7 @@ def main():
                    "w_full_per_step": w_full},
         "roofline": {
             "bound": "alu",
-            "kernel": "greedy_persistent",
+            "kernel": "greedy_code_kernel",
             "achieved": round(achieved, 3),
             "peak": round(PEAK_GCHECKS, 1),
             "unit": "Gchecks/s",
@@ -163,6 +303,13 @@ def main():
         "executed_checks_per_step": executed // args.steps,
         "naive_equivalent_gchecks_per_s": round(args.steps * w_full / wall / 1e9, 3),
     }
+    progress(f"sweep done: {wall:.2f} s for {args.steps} steps")
+    if not args.no_batched:
+        line["batched"] = bench_batched(gc, torch, max(args.steps, 3), args.warmup)
+        progress("batched done")
+    if not args.no_served:
+        line["served"] = bench_served(gc, torch, args.served_jobs, args.served_arena_mib << 20,
+                                      args.served_teams, args.served_load)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

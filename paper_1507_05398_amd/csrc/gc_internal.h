@@ -90,7 +90,11 @@ struct Params {
 
 size_t team_workspace_bytes();
 int device_info(int dev, int *cus, int *coop, int *blocks_per_cu);
-hipError_t launch_persistent(const Params &P, unsigned int grid, hipStream_t stream);
+// Which kernel symbol a persistent launch uses (same code; separate names in
+// profiles).
+enum class LaunchKind { kSingle, kBatch, kServer };
+
+hipError_t launch_persistent(const Params &P, unsigned int grid, hipStream_t stream, LaunchKind kind);
 hipError_t launch_init(Bar *bar, DevQueue *dq, int reset_queue, hipStream_t stream);
 int fail(int code, const char *fmt, ...);
 extern thread_local std::string g_error;

@@ -124,7 +124,7 @@ int launch_server_kernel(gc_server *s) {
   P.team_ws = s->team_ws;
   P.team_ws_stride = team_workspace_bytes();
   hipError_t e = launch_init(s->bar, s->dq, 0, s->stream);
-  if (e == hipSuccess) e = launch_persistent(P, s->grid, s->stream);
+  if (e == hipSuccess) e = launch_persistent(P, s->grid, s->stream, LaunchKind::kServer);
   if (e == hipSuccess) e = hipEventRecord(s->kernel_done, s->stream);
   if (e != hipSuccess) return fail(GC_EDEVICE, "server launch failed: %s", hipGetErrorString(e));
   s->launched = true;
