@@ -155,7 +155,10 @@ int greedy_code_batch(gc_job *jobs, int njobs, int teams, void *hip_stream, floa
  * serialised by an internal lock. */
 typedef struct gc_server gc_server;
 
-/* arena_bytes: device memory for resident codes; teams: 1, 2, 4 or 8. */
+/* arena_bytes: device memory for resident codes (the server also allocates
+ * as much pinned host memory: each finished code is written there by the
+ * kernel itself, so fetching a result needs no device copy while the kernel
+ * holds the GPU); teams: 1, 2, 4 or 8. */
 int gc_server_create(size_t arena_bytes, int teams, gc_server **out);
 /* Queue a job; *ticket identifies it.  GC_ENOMEM if its worst-case code can
  * never fit the arena. */
@@ -164,7 +167,8 @@ int gc_server_submit(gc_server *srv, int n, int d, int ordering, uint64_t *ticke
 int gc_server_poll(gc_server *srv, uint64_t ticket, int *state, uint64_t *count);
 /* Device address of a finished job's words (valid until released). */
 int gc_server_words(gc_server *srv, uint64_t ticket, const uint32_t **d_words, uint64_t *count);
-/* Copy a finished job's words into host memory (cap words available). */
+/* Copy a finished job's words into host memory (cap words available); a host
+ * memcpy from the pinned mirror. */
 int gc_server_fetch(gc_server *srv, uint64_t ticket, uint32_t *host_words, uint64_t cap,
                     uint64_t *count);
 /* Work counters and device time of a finished job (either may be NULL). */

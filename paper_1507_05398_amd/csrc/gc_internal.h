@@ -26,6 +26,8 @@ struct Job {
   uint32_t *code;                 // device array of `capacity` words (16-byte aligned)
   unsigned long long capacity;
   unsigned long long *count;      // device counter written at completion (may be null)
+  uint32_t *host_copy;            // device-visible pinned host array that receives the words
+                                  // before `done` is set (may be null)
   // outputs
   unsigned long long out_count;
   unsigned long long windows, rounds, survivors, chk_near, chk_deep, chk_pairs;

@@ -50,6 +50,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -143,6 +145,7 @@ struct Lds {
   // job
   int job, n, d, ord, mode;
   uint32_t *code;
+  uint32_t *host_copy;                 // server: pinned host copy of the words (or null)
   unsigned long long capacity, total, near_depth;
   unsigned int target;
   // window
@@ -997,6 +1000,26 @@ __device__ __forceinline__ void persistent_body(Lds &L, const Params &P) {
     team_barrier(L, P, P.spin_limit);
     if (L.abort) break;
 
+    // Server jobs also get their words in pinned host memory: the team writes
+    // them over the fabric (no copy engine or extra kernel is needed while this
+    // kernel holds the GPU), then releases them at system scope before the
+    // barrier that precedes `done`.
+    if (tid == 0) L.host_copy = ld_sys(&P.jobs[L.job].host_copy);
+    __syncthreads();
+    if (L.host_copy != nullptr && ld_relaxed(&W.ctl->status) == 0) {
+      const unsigned long long m = ld_relaxed(&W.ctl->m);
+      const uint4 *src = reinterpret_cast<const uint4 *>(L.code);
+      uint4 *dst = reinterpret_cast<uint4 *>(L.host_copy);
+      const unsigned long long stride = (unsigned long long)L.team_size * kBlock;
+      for (unsigned long long k = (unsigned long long)L.team_rank * kBlock + tid; k < m / 4; k += stride)
+        dst[k] = src[k];
+      for (unsigned long long k = m / 4 * 4 + (unsigned long long)L.team_rank * kBlock + tid; k < m; k += stride)
+        L.host_copy[k] = L.code[k];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+      team_barrier(L, P, P.spin_limit);
+      if (L.abort) break;
+    }
+
     // Completion: outputs first, then `done` with system-scope release, so a
     // host that sees done=1 also sees the words and the count.
     if (L.team_rank == 0 && tid == 0) {
@@ -1346,9 +1369,22 @@ int greedy_code_batch(gc_job *jobs, int njobs, int teams, void *hip_stream, floa
       return fail(GC_EINVAL, "job %d: d_words must be a 16-byte aligned device array", i);
     fill_job(&J[i], g.n, g.d, g.ordering, g.d_words, g.capacity, g.d_count, nullptr);
   }
+  // Teams claim jobs in queue order; the queue holds the jobs longest first
+  // (by the exhaustive-scan work bound 2^n * capacity), so that the largest
+  // codes do not start last and stretch the launch.
+  std::vector<int> order((size_t)njobs);
+  std::vector<double> est((size_t)njobs);
+  for (int i = 0; i < njobs; ++i) {
+    order[i] = i;
+    est[i] = std::ldexp((double)greedy_code_capacity(J[i].n, J[i].d), J[i].n);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return est[a] > est[b]; });
+  std::vector<Job> Q((size_t)njobs);
+  for (int k = 0; k < njobs; ++k) Q[k] = J[order[k]];
   float ms = 0.f;
-  int rc = run_batch(J.data(), njobs, teams, 0, (hipStream_t)hip_stream, &ms, LaunchKind::kBatch);
+  int rc = run_batch(Q.data(), njobs, teams, 0, (hipStream_t)hip_stream, &ms, LaunchKind::kBatch);
   if (kernel_ms) *kernel_ms = ms;
+  for (int k = 0; k < njobs; ++k) J[order[k]] = Q[k];
   for (int i = 0; i < njobs; ++i) {
     jobs[i].count = J[i].out_count;
     jobs[i].status = J[i].done ? J[i].status : GC_ETIMEOUT;

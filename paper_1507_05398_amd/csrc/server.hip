@@ -56,6 +56,10 @@ struct gc_server {
   char *team_ws = nullptr;
   char *arena = nullptr;
   size_t arena_bytes = 0;
+  // pinned host mirror of the arena: the kernel writes each finished code
+  // there too, so fetching a result needs no device copy
+  char *mirror = nullptr;
+  char *mirror_dev = nullptr;
   // pinned host (device-visible)
   gcimpl::HostQueue *hq = nullptr;
   gcimpl::Job *jobs = nullptr;
@@ -156,6 +160,7 @@ int pump(gc_server *s) {
     J->code = reinterpret_cast<uint32_t *>(s->arena + off);
     J->capacity = greedy_code_capacity(t.n, t.d);
     J->count = nullptr;
+    J->host_copy = reinterpret_cast<uint32_t *>(s->mirror_dev + off);
     s->slot_ticket[t.slot] = id;
     s->inflight.insert(id);
     ++s->published;
@@ -219,6 +224,9 @@ int gc_server_create(size_t arena_bytes, int teams, gc_server **out) {
     e = hipHostMalloc((void **)&s->hq, sizeof(HostQueue), hipHostMallocCoherent | hipHostMallocMapped);
   if (e == hipSuccess)
     e = hipHostMalloc((void **)&s->jobs, sizeof(Job) * kServerSlots, hipHostMallocCoherent | hipHostMallocMapped);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void **)&s->mirror, s->arena_bytes, hipHostMallocCoherent | hipHostMallocMapped);
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&s->mirror_dev, s->mirror, 0);
   if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&s->hq_dev, s->hq, 0);
   if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&s->jobs_dev, s->jobs, 0);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
@@ -296,8 +304,11 @@ int gc_server_fetch(gc_server *s, uint64_t ticket, uint32_t *host_words, uint64_
   if (m > cap) return fail(GC_ECAPACITY, "code has %llu words, buffer %llu", (unsigned long long)m,
                            (unsigned long long)cap);
   if (!host_words && m) return fail(GC_EINVAL, "host_words is NULL");
-  hipError_t e = hipMemcpy(host_words, dw, m * sizeof(uint32_t), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return fail(GC_EDEVICE, "hipMemcpy failed: %s", hipGetErrorString(e));
+  // The kernel wrote the words to the host mirror before publishing `done`
+  // (observed with acquire by gc_server_words), so this is a host copy.
+  std::lock_guard<std::mutex> lk(s->mu);
+  const size_t off = reinterpret_cast<const char *>(dw) - s->arena;
+  if (m) memcpy(host_words, s->mirror + off, m * sizeof(uint32_t));
   return GC_OK;
 }
 
@@ -371,6 +382,7 @@ int gc_server_destroy(gc_server *s) {
   if (s->jobs) (void)hipHostFree(s->jobs);
   if (s->hq) (void)hipHostFree(s->hq);
   if (s->arena) (void)hipFree(s->arena);
+  if (s->mirror) (void)hipHostFree(s->mirror);
   if (s->dev) (void)hipFree(s->dev);
   delete s;
   return GC_OK;
