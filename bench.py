@@ -11,7 +11,22 @@ with d=7 (64 instances).  ``--workload large`` runs the n=26/28 d=3 screens
 The headline value is algorithmic distance checks per second: the sum over
 instances of W_ee (checks done by a sequential newest-first scan with early
 exit, counted by the CPU oracle and stored in tests/golden/expected_codes.txt)
-divided by the wall time of the step.  Output: one JSON line.
+divided by the wall time of the step.
+
+Also measured (one JSON line in all):
+  * batched: the 256-instance workload (seed 1507) as one persistent launch
+    against a loop of plain per-instance calls on the same buffers;
+  * served: a seeded Poisson stream of 10,000 jobs through the job server
+    (continuous batching), with p50/p99 latency, against the same jobs one at
+    a time;
+  * roofline of greedy_code_kernel, the single-code kernel: every launch of it
+    in this run (the sweep and the plain per-instance loop), algorithmic
+    checks (W_ee) per launch over the launch's duration (HIP events on the
+    launch stream, recorded by the library);
+  * cpu_baseline: the oracle on a bounded sample, one host thread.
+
+``--copy-calibration`` only runs a device copy of known size (for scaling
+the FETCH_SIZE / WRITE_SIZE counters) and prints its bytes.
 """
 import argparse
 import hashlib
@@ -29,6 +44,10 @@ ORDS = ["lex", "gray", "grlex", "grevlex"]
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 OPS_PER_CHECK = 2.5
 PEAK_GCHECKS = VALU_LANE_OPS / OPS_PER_CHECK / 1e9
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def sweep_instances():
@@ -55,6 +74,40 @@ def load_expected():
     return out
 
 
+def load_expected_batch():
+    path = os.path.join(ROOT, "tests", "golden", "expected_batch.txt")
+    out = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            idx, key, m, digest, w_ee, w_full = line.split()
+            out[int(idx)] = (key, int(m), digest, int(w_ee), int(w_full))
+    return out
+
+
+def digest_of(t):
+    return hashlib.sha256(t.cpu().numpy().astype("<u4").tobytes()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per greedy_code_kernel launch from the committed counter
+    summary, or None when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "greedy_code_kernel_sweep_batched_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+            k, v = line.split(":", 1)
+            fields[k] = v.strip()
+    h = hashlib.sha256()
+    for name in ("greedy_code.hip", "gc_internal.h"):
+        with open(os.path.join(ROOT, "paper_1507_05398_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if fields.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline():
     """The CPU oracle (plain sequential scan, one thread) on a bounded sample
     of the sweep: n=20, d in {3, 5}, lex and Gray."""
@@ -71,28 +124,60 @@ def cpu_baseline():
                       f"{checks:.3e} checks in {dt:.1f} s)"}
 
 
-def progress(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+class LaunchLog:
+    """Kernel time and algorithmic checks of every timed greedy_code_kernel
+    launch."""
+
+    def __init__(self):
+        self.ms, self.w_ee, self.executed, self.launches = 0.0, 0, 0, 0
+
+    def add(self, stats, w_ee):
+        self.ms += stats["kernel_ms"]
+        self.w_ee += w_ee
+        self.executed += stats["checks_near"] + stats["checks_deep"] + stats["checks_pairs"]
+        self.launches += 1
+
+    def gchecks(self):
+        return self.w_ee / (self.ms / 1e3) / 1e9 if self.ms else 0.0
 
 
-def load_expected_batch():
-    path = os.path.join(ROOT, "tests", "golden", "expected_batch.txt")
-    out = {}
-    for line in open(path):
-        if line.strip() and not line.startswith("#"):
-            idx, key, m, digest, w_ee, w_full = line.split()
-            out[int(idx)] = (key, int(m), digest, int(w_ee), int(w_full))
-    return out
+def bench_sweep(gc, torch, insts, expected, steps, warmup, log):
+    bufs = []
+    for n, d, o in insts:
+        cap = gc.greedy_code_capacity(n, d)
+        bufs.append((torch.empty(cap, dtype=torch.int32, device="cuda"),
+                     torch.zeros(1, dtype=torch.int64, device="cuda")))
+    stream = torch.cuda.current_stream()
+    own = LaunchLog()
+
+    def one_step(record):
+        for (n, d, o), (w, c) in zip(insts, bufs):
+            st = gc.greedy_code_device_ex(n, d, o, w, c, stream=stream)
+            if record:
+                own.add(st, expected[f"{n}_{d}_{o}"][2])
+                log.add(st, expected[f"{n}_{d}_{o}"][2])
+
+    for _ in range(warmup):
+        one_step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # Bit-exact check of the last step's output (outside the timed region).
+    for (n, d, o), (w, c) in zip(insts, bufs):
+        m, dig, _, _ = expected[f"{n}_{d}_{o}"]
+        got = w[: int(c.item())]
+        if len(got) != m or digest_of(got) != dig:
+            raise SystemExit(f"MISMATCH n={n} d={d} {o}: {len(got)} words vs {m}")
+    return wall, own
 
 
-def digest_of(t):
-    return hashlib.sha256(t.cpu().numpy().astype("<u4").tobytes()).hexdigest()
-
-
-def bench_batched(gc, torch, steps, warmup):
+def bench_batched(gc, torch, steps, warmup, log):
     """The 256-instance batched workload (seed 1507): one persistent launch
-    over every instance (teams by job count) against a loop of plain
-    per-instance calls on the same preallocated buffers."""
+    over every instance (teams by job count, largest jobs first) against a
+    loop of plain per-instance calls on the same preallocated buffers."""
     from paper_1507_05398_amd import workloads
     insts = workloads.batched_instances()
     expected = load_expected_batch()
@@ -111,16 +196,18 @@ def bench_batched(gc, torch, steps, warmup):
         if len(t) != m or digest_of(t) != dig:
             raise SystemExit(f"BATCH MISMATCH job {i} ({key})")
 
-    def plain():
-        for (n, d, o), (w, c) in zip(insts, plan.bufs):
-            gc.greedy_code_device(n, d, o, w, c, stream=stream)
+    def plain(record):
+        for i, ((n, d, o), (w, c)) in enumerate(zip(insts, plan.bufs)):
+            st = gc.greedy_code_device_ex(n, d, o, w, c, stream=stream)
+            if record:
+                log.add(st, expected[i][3])
     for _ in range(warmup):
-        plain()
+        plain(False)
     torch.cuda.synchronize()
     pwalls = []
     for _ in range(steps):
         t0 = time.perf_counter()
-        plain()
+        plain(True)
         torch.cuda.synchronize()
         pwalls.append(time.perf_counter() - t0)
     for i, (w, c) in enumerate(plan.bufs):
@@ -137,19 +224,28 @@ def bench_batched(gc, torch, steps, warmup):
             "batched_gchecks_per_s": round(w_ee / tb / 1e9, 3)}
 
 
-def bench_served(gc, torch, njobs, arena_bytes, teams, load_frac):
+def bench_served(gc, njobs, arena_bytes, teams, load_frac):
     """The served workload: seeded Poisson stream of `njobs` jobs (n in
-    [10, 26] skewed small, d in [3, 10], random ordering).  Three passes: the
-    jobs one at a time through the plain host entry point (serial), all jobs
-    submitted at once to the server (its capacity), then the Poisson stream
-    at `load_frac` of that capacity.  Latency = arrival -> words in host
-    memory.  Every served result must equal the serial one."""
+    [10, 26] skewed small, d in [3, 10], random ordering).  Three passes:
+    one job in flight at a time (serial: one team spanning the GPU), all
+    jobs submitted at once (capacity), then the Poisson stream at
+    `load_frac` of that capacity.  Latency = arrival -> words in host memory.
+    Every result of the concurrent passes must equal the serial one."""
     from paper_1507_05398_amd import workloads
     unit = workloads.served_jobs(seed=1507, count=njobs, rate=1.0)
     ref = []
+
+    def sha(words):
+        return hashlib.sha256(words.astype("<u4").tobytes()).hexdigest()
+
     t0 = time.perf_counter()
-    for _, n, d, o in unit:
-        ref.append(hashlib.sha256(gc.greedy_code(n, d, o).astype("<u4").tobytes()).hexdigest())
+    with gc.Server(arena_bytes=arena_bytes, teams=1) as srv:
+        for _, n, d, o in unit:
+            tk = srv.submit(n, d, o)
+            while srv.poll(tk)[0] < gc.GC_JOB_DONE:
+                pass
+            ref.append(sha(srv.fetch(tk)))
+            srv.release(tk)
     serial_s = time.perf_counter() - t0
     progress(f"served: serial pass {serial_s:.2f} s")
 
@@ -179,7 +275,7 @@ def bench_served(gc, torch, njobs, arena_bytes, teams, load_frac):
                     lat[i] = t_fin - arrivals[i]
                     finish.append(t_fin)
                     srv.release(tk)
-                    if hashlib.sha256(words.astype("<u4").tobytes()).hexdigest() != ref[i]:
+                    if sha(words) != ref[i]:
                         raise SystemExit(f"SERVED MISMATCH job {i} {unit[i][1:]}")
                     done += 1
                     progressed = True
@@ -211,6 +307,18 @@ def bench_served(gc, torch, njobs, arena_bytes, teams, load_frac):
             "polls_waiting_for_memory": waits}
 
 
+def copy_calibration(torch, mib):
+    """A plain device copy of `mib` MiB, five times (the FETCH_SIZE and
+    WRITE_SIZE of this kernel scale the counters of the others)."""
+    n = (mib << 20) // 4
+    src = torch.arange(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_launch": n * 4, "launches": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,6 +332,9 @@ def main():
     ap.add_argument("--served-arena-mib", type=int, default=64)
     ap.add_argument("--served-teams", type=int, default=8)
     ap.add_argument("--served-load", type=float, default=0.7)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
+    ap.add_argument("--host-api", action="store_true",
+                    help="also time one step through the host-memory entry point")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -235,54 +346,26 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration(torch, args.copy_calibration)
+        return
+    gc.load()
     expected = load_expected()
     insts = sweep_instances() if args.workload == "sweep" else large_instances()
     missing = [i for i in insts if f"{i[0]}_{i[1]}_{i[2]}" not in expected]
     if missing:
         raise SystemExit(f"no oracle reference for {missing}")
-    bufs = []
-    for n, d, o in insts:
-        cap = gc.greedy_code_capacity(n, d)
-        bufs.append((torch.empty(cap, dtype=torch.int32, device="cuda"),
-                     torch.zeros(1, dtype=torch.int64, device="cuda")))
-    stream = torch.cuda.current_stream()
 
-    def one_step():
-        stats = []
-        for (n, d, o), (w, c) in zip(insts, bufs):
-            stats.append(gc.greedy_code_device_ex(n, d, o, w, c, stream=stream))
-        return stats
-
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    kernel_ms = 0.0
-    executed = 0
-    for _ in range(args.steps):
-        for st in one_step():
-            kernel_ms += st["kernel_ms"]
-            executed += st["checks_near"] + st["checks_deep"] + st["checks_pairs"]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
-    # Bit-exact check of the last step's output (outside the timed region).
-    for (n, d, o), (w, c) in zip(insts, bufs):
-        m, dig, _, _ = expected[f"{n}_{d}_{o}"]
-        got = w[: int(c.item())].cpu().numpy().astype("<u4")
-        if len(got) != m or hashlib.sha256(got.tobytes()).hexdigest() != dig:
-            raise SystemExit(f"MISMATCH n={n} d={d} {o}: {len(got)} words vs {m}")
-
+    log = LaunchLog()
+    wall, sweep = bench_sweep(gc, torch, insts, expected, args.steps, args.warmup, log)
+    progress(f"{args.workload} done: {wall:.2f} s for {args.steps} steps")
     w_ee = sum(expected[f"{n}_{d}_{o}"][2] for n, d, o in insts)
     w_full = sum(expected[f"{n}_{d}_{o}"][3] for n, d, o in insts)
-    value = args.steps * w_ee / wall / 1e9
-    launches = args.steps * len(insts)
-    achieved = args.steps * w_ee / (kernel_ms / 1e3) / 1e9
     name = ("sweep: lex/gray/grlex/grevlex x n{20,22,24} x d{3,4,5,6,8} + n23 d7 (64 instances)"
             if args.workload == "sweep" else "large: lex/gray x n{26,28} x d3 (4 instances)")
     line = {
         "metric": "Gdist-checks/s (algorithmic W_ee checks per second)",
-        "value": round(value, 3),
+        "value": round(args.steps * w_ee / wall / 1e9, 3),
         "unit": "Gchecks/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -295,26 +378,42 @@ def main():
         "data": "synthetic: the full space F_2^n in each ordering (no dataset)",
         "config": {"workload": name, "instances": len(insts), "w_ee_per_step": w_ee,
                    "w_full_per_step": w_full},
-        "roofline": {
-            "bound": "alu",
-            "kernel": "greedy_code_kernel",
-            "achieved": round(achieved, 3),
-            "peak": round(PEAK_GCHECKS, 1),
-            "unit": "Gchecks/s",
-            "frac": round(achieved / PEAK_GCHECKS, 5),
-            "traffic": None,
-            "launches": launches,
-            "avg_launch_ms": round(kernel_ms / launches, 4),
-        },
-        "executed_checks_per_step": executed // args.steps,
-        "naive_equivalent_gchecks_per_s": round(args.steps * w_full / wall / 1e9, 3),
     }
-    progress(f"sweep done: {wall:.2f} s for {args.steps} steps")
+    if args.host_api:
+        # The same step through the host-memory entry point (device
+        # allocation, build and copy of the words over PCIe).  Off by default:
+        # its launches are not in the roofline's launch log.
+        t0 = time.perf_counter()
+        for n, d, o in insts:
+            gc.greedy_code(n, d, o)
+        host_wall = time.perf_counter() - t0
+        line["host_api_gchecks_per_s"] = round(w_ee / host_wall / 1e9, 3)
+    batched = None
     if not args.no_batched:
-        line["batched"] = bench_batched(gc, torch, max(args.steps, 3), args.warmup)
+        batched = bench_batched(gc, torch, max(args.steps, 3), args.warmup, log)
         progress("batched done")
+    line["roofline"] = {
+        "bound": "alu",
+        "kernel": "greedy_code_kernel",
+        "achieved": round(log.gchecks(), 3),
+        "peak": round(PEAK_GCHECKS, 1),
+        "unit": "Gchecks/s",
+        "frac": round(log.gchecks() / PEAK_GCHECKS, 5),
+        "traffic": measured_traffic(),
+        "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE, copy-calibrated)",
+        "launches": log.launches,
+        "avg_launch_ms": round(log.ms / max(log.launches, 1), 4),
+        "covers": "timed launches of the sweep" + (" and of the plain batched loop" if batched else ""),
+        "sweep_only": {"achieved": round(sweep.gchecks(), 3),
+                       "frac": round(sweep.gchecks() / PEAK_GCHECKS, 5),
+                       "avg_launch_ms": round(sweep.ms / max(sweep.launches, 1), 4)},
+    }
+    line["executed_checks_per_step"] = sweep.executed // max(args.steps, 1)
+    line["naive_equivalent_gchecks_per_s"] = round(args.steps * w_full / wall / 1e9, 3)
+    if batched:
+        line["batched"] = batched
     if not args.no_served:
-        line["served"] = bench_served(gc, torch, args.served_jobs, args.served_arena_mib << 20,
+        line["served"] = bench_served(gc, args.served_jobs, args.served_arena_mib << 20,
                                       args.served_teams, args.served_load)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
