@@ -133,7 +133,7 @@ typedef struct gc_job {
     double device_ms;
 } gc_job;
 
-/* Build many codes (BASELINE batched workload; no paper counterpart: the paper
+/* Build many codes (batched workload; no paper counterpart: the paper
  * builds one code per run) in one persistent launch on `hip_stream`: the
  * workgroups form `teams` teams (1, 2, 4 or 8; 0 = choose by job count) by
  * XCD and each team pulls the next job from a device queue, so codes of
@@ -143,7 +143,48 @@ typedef struct gc_job {
  * kernel_ms (may be NULL) receives the device time of the launch. */
 int greedy_code_batch(gc_job *jobs, int njobs, int teams, void *hip_stream, float *kernel_ms);
 
-/* Job server (BASELINE served workload; no paper counterpart): continuous
+/* Captured batch (no paper counterpart): the batch launch of `jobs` (same
+ * rules as greedy_code_batch, tunings as remembered at creation) recorded once
+ * into a HIP graph -- job-table upload from pinned host memory, reset kernel,
+ * cooperative persistent launch, download of the outputs into pinned host
+ * memory -- so that each rebuild of the same codes is one hipGraphLaunch.
+ * The graph keeps the jobs' d_words / d_count pointers: those buffers must
+ * stay allocated while it exists.  Allocates its device workspace and pinned
+ * buffers at creation and nothing afterwards. */
+typedef struct gc_batch_graph gc_batch_graph;
+int gc_batch_graph_create(const gc_job *jobs, int njobs, int teams, gc_batch_graph **out);
+/* Enqueue one replay on `hip_stream` (asynchronous). */
+int gc_batch_graph_launch(gc_batch_graph *graph, void *hip_stream);
+/* After the replay's stream has synchronized: per-job status, count and
+ * device_ms into jobs[0..njobs) (the array given at creation, same order).
+ * Returns GC_OK or the first failing job's code. */
+int gc_batch_graph_results(gc_batch_graph *graph, gc_job *jobs);
+/* Free the graph (no replay may be in flight). */
+int gc_batch_graph_destroy(gc_batch_graph *graph);
+
+/* Autotuner (no paper counterpart).  Builds (n, d, ordering) once per
+ * candidate tuning on `hip_stream` (near-screen depth of the whole code or the
+ * newest 65536, 16384 or 4096 words, with either deep-scan policy, then the
+ * fastest of those with a larger window), checks that every candidate built
+ * the same code word for word, and returns the fastest in *best (its device
+ * time in *best_ms, may be NULL).  The choice is remembered per device and
+ * (n, d, ordering): later builds of that instance that pass no tuning
+ * (greedy_code, greedy_code_device, greedy_code_device_ex with tuning NULL,
+ * batch jobs, server jobs) use it.  Allocates a scratch code buffer on the
+ * stream for the duration of the call.  d <= 1 or d > n: nothing to tune,
+ * *best is zeroed.  GC_EDEVICE if two candidates disagree. */
+int greedy_code_tune(int n, int d, int ordering, void *hip_stream, gc_tuning *best, float *best_ms);
+
+/* Forget every remembered tuning (builds return to the built-in defaults). */
+void greedy_code_tune_reset(void);
+
+/* Team-count tuner for a batch: runs greedy_code_batch with 1, 2, 4 and 8
+ * teams and returns the fastest count in *best_teams (device time in
+ * *best_ms, may be NULL).  The jobs' outputs are those of the last run (every
+ * run builds the same codes). */
+int greedy_code_batch_tune(gc_job *jobs, int njobs, void *hip_stream, int *best_teams, float *best_ms);
+
+/* Job server (served workload; no paper counterpart): continuous
  * batching over one persistent launch.  Callers: anything that wants codes
  * built as requests arrive.  A job is admitted once the device arena has room
  * for its worst-case code (greedy_code_capacity(n, d) words); admitted jobs

@@ -20,7 +20,9 @@ GC_JOB_WAITING, GC_JOB_ADMITTED, GC_JOB_DONE, GC_JOB_FAILED = 0, 1, 2, 3
 
 # Every symbol declared in include/greedy_code.h.
 EXPORTS = ["greedy_code_capacity", "greedy_code", "greedy_code_device", "greedy_code_device_ex",
-           "greedy_code_batch", "gc_server_create", "gc_server_submit", "gc_server_poll",
+           "greedy_code_batch", "greedy_code_tune", "greedy_code_tune_reset",
+           "greedy_code_batch_tune", "gc_batch_graph_create", "gc_batch_graph_launch",
+           "gc_batch_graph_results", "gc_batch_graph_destroy", "gc_server_create", "gc_server_submit", "gc_server_poll",
            "gc_server_words", "gc_server_fetch", "gc_server_stats", "gc_server_release",
            "gc_server_drain", "gc_server_destroy", "gc_last_error", "gc_version"]
 
@@ -83,6 +85,23 @@ def load():
     lib.greedy_code_batch.argtypes = [ctypes.POINTER(GcJob), ctypes.c_int, ctypes.c_int, vp,
                                       ctypes.POINTER(ctypes.c_float)]
     lib.greedy_code_batch.restype = ctypes.c_int
+    lib.greedy_code_tune.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
+                                     ctypes.POINTER(GcTuning), ctypes.POINTER(ctypes.c_float)]
+    lib.greedy_code_tune.restype = ctypes.c_int
+    lib.greedy_code_tune_reset.argtypes = []
+    lib.greedy_code_tune_reset.restype = None
+    lib.greedy_code_batch_tune.argtypes = [ctypes.POINTER(GcJob), ctypes.c_int, vp,
+                                           ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float)]
+    lib.greedy_code_batch_tune.restype = ctypes.c_int
+    lib.gc_batch_graph_create.argtypes = [ctypes.POINTER(GcJob), ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_void_p)]
+    lib.gc_batch_graph_create.restype = ctypes.c_int
+    lib.gc_batch_graph_launch.argtypes = [vp, vp]
+    lib.gc_batch_graph_launch.restype = ctypes.c_int
+    lib.gc_batch_graph_results.argtypes = [vp, ctypes.POINTER(GcJob)]
+    lib.gc_batch_graph_results.restype = ctypes.c_int
+    lib.gc_batch_graph_destroy.argtypes = [vp]
+    lib.gc_batch_graph_destroy.restype = ctypes.c_int
     lib.gc_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
     lib.gc_server_create.restype = ctypes.c_int
     lib.gc_server_submit.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, u64p]
@@ -206,6 +225,21 @@ def greedy_code_batch(instances, teams=0, stream=None, device="cuda"):
     return out, info, ms.value
 
 
+def greedy_code_tune(n: int, d: int, ordering, stream=None) -> dict:
+    """Autotune (n, d, ordering) on the device; the choice is remembered by the
+    library for later builds of that instance.  Returns the chosen tuning and
+    its device time."""
+    best, ms = GcTuning(), ctypes.c_float()
+    _check(load().greedy_code_tune(n, d, _ordering(ordering), _stream_ptr(stream), ctypes.byref(best),
+                                   ctypes.byref(ms)))
+    return {"near_depth": best.near_depth, "target_survivors": best.target_survivors,
+            "grid_blocks": best.grid_blocks, "resolve_mode": best.resolve_mode, "ms": ms.value}
+
+
+def greedy_code_tune_reset() -> None:
+    load().greedy_code_tune_reset()
+
+
 class BatchPlan:
     """Reusable batch: output buffers and the job table are allocated once,
     so repeated runs time only the launch."""
@@ -232,6 +266,17 @@ class BatchPlan:
         _check(rc)
         return ms.value
 
+    def tune(self, stream=None):
+        """Try 1, 2, 4 and 8 teams; returns (best team count, its device ms)."""
+        best, ms = ctypes.c_int(), ctypes.c_float()
+        _check(load().greedy_code_batch_tune(self.jobs, len(self.instances), _stream_ptr(stream),
+                                             ctypes.byref(best), ctypes.byref(ms)))
+        return best.value, ms.value
+
+    def graph(self, teams=0):
+        """Capture this batch into a replayable HIP graph (BatchGraph)."""
+        return BatchGraph(self, teams)
+
     def results(self):
         """Per job: uint32 CUDA tensor trimmed to |C|."""
         return [w[: int(self.jobs[i].count)] for i, (w, _) in enumerate(self.bufs)]
@@ -239,6 +284,37 @@ class BatchPlan:
     def info(self):
         return [{"status": self.jobs[i].status, "count": int(self.jobs[i].count),
                  "device_ms": self.jobs[i].device_ms} for i in range(len(self.instances))]
+
+
+class BatchGraph:
+    """A BatchPlan's launch captured into a HIP graph: launch() enqueues a
+    replay, wait() synchronizes the stream and collects the job outputs."""
+
+    def __init__(self, plan, teams=0):
+        self.plan = plan
+        self._h = ctypes.c_void_p()
+        _check(load().gc_batch_graph_create(plan.jobs, len(plan.instances), teams, ctypes.byref(self._h)))
+
+    def launch(self, stream=None):
+        self._stream = stream
+        _check(load().gc_batch_graph_launch(self._h, _stream_ptr(stream)))
+
+    def wait(self):
+        import torch
+        s = getattr(self, "_stream", None)
+        (s or torch.cuda.current_stream()).synchronize()
+        _check(load().gc_batch_graph_results(self._h, self.plan.jobs))
+
+    def close(self):
+        if self._h:
+            load().gc_batch_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Server:

@@ -8,6 +8,8 @@
 
 #include <string>
 
+#include "greedy_code.h"
+
 namespace gcimpl {
 
 constexpr int kBlock = 1024;   // threads per workgroup
@@ -99,6 +101,17 @@ enum class LaunchKind { kSingle, kBatch, kServer };
 hipError_t launch_persistent(const Params &P, unsigned int grid, hipStream_t stream, LaunchKind kind);
 hipError_t launch_init(Bar *bar, DevQueue *dq, int reset_queue, hipStream_t stream);
 int fail(int code, const char *fmt, ...);
+// Tuning remembered by greedy_code_tune for (current device, n, d, ordering).
+bool tuned_for(int n, int d, int ordering, gc_tuning *out);
+// Helpers shared by the entry points.
+int check_job_args(int n, int d, int ordering);
+int pick_grid(unsigned int requested, unsigned int *grid);
+unsigned int spin_limit_from_env();
+void fill_job(Job *J, int n, int d, int ordering, uint32_t *words, uint64_t capacity, uint64_t *count,
+              const gc_tuning *tuning);
+// Validates a caller's job array and fills `J` (caller order) and `order`
+// (queue position -> caller index, longest jobs first).
+int prepare_batch(const gc_job *jobs, int njobs, Job *J, int *order);
 extern thread_local std::string g_error;
 
 }  // namespace gcimpl

@@ -52,6 +52,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -68,7 +69,6 @@ constexpr int kTile = 1024;                           // candidates per screen t
 constexpr int kRows = kTile / 64;
 constexpr int kSegMax = 64 * 64;                      // longest code segment staged at once (words)
 constexpr int kSegLoads = kSegMax / kBlock;           // words each thread stages per segment
-constexpr unsigned long long kPartQuantum = 1024;     // code words per part of a split range, at least
 constexpr int kSMax = 1024;                           // survivors per window (resolve capacity)
 constexpr int kNb = kSMax / 64;                       // survivor blocks of 64
 constexpr int kAdjWords = 64 * kNb * (kNb + 1) / 2;   // lower-triangular block adjacency
@@ -86,6 +86,7 @@ enum : int { MODE_AUTO = 0, MODE_TENTATIVE = 1, MODE_DEEP_ALL = 2 };
 // Per-team workspace, carved out of one buffer.
 struct TeamWs {
   Ctl *ctl;
+  unsigned long long *cur;   // kCursors range cursors: near-screen tiles, then deep tiles
   uint32_t *win_dead;        // kWMax / 32
   unsigned long long *adj;   // kAdjWords
   uint32_t *deep_word;       // kSMax
@@ -94,8 +95,12 @@ struct TeamWs {
 };
 
 constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+constexpr int kNearTiles = (int)(kWMax / kTile);       // tiles of a window
+constexpr int kDeepTiles = (kSMax + kTile - 1) / kTile;  // tiles of a deep list
+constexpr int kCursors = kNearTiles + kDeepTiles;
 constexpr size_t kOffCtl = 0;
-constexpr size_t kOffDead = align256(sizeof(Ctl));
+constexpr size_t kOffCur = align256(sizeof(Ctl));
+constexpr size_t kOffDead = kOffCur + align256(kCursors * sizeof(unsigned long long));
 constexpr size_t kOffAdj = kOffDead + align256(kWMax / 32 * sizeof(uint32_t));
 constexpr size_t kOffDword = kOffAdj + align256(kAdjWords * sizeof(unsigned long long));
 constexpr size_t kOffDidx = kOffDword + align256(kSMax * sizeof(uint32_t));
@@ -105,6 +110,7 @@ constexpr size_t kTeamWsBytes = kOffDfail + align256(kSMax / 32 * sizeof(uint32_
 __host__ __device__ inline TeamWs team_ws(char *base) {
   TeamWs w;
   w.ctl = reinterpret_cast<Ctl *>(base + kOffCtl);
+  w.cur = reinterpret_cast<unsigned long long *>(base + kOffCur);
   w.win_dead = reinterpret_cast<uint32_t *>(base + kOffDead);
   w.adj = reinterpret_cast<unsigned long long *>(base + kOffAdj);
   w.deep_word = reinterpret_cast<uint32_t *>(base + kOffDword);
@@ -128,6 +134,7 @@ struct TileLds {
   uint32_t ci[2][kTile];
   unsigned long long killw[kWaves][kRows];
   unsigned int wcnt[kWaves];
+  unsigned long long claim[2];         // offsets (from the newest end) of claimed segments, by parity
 };
 
 // In-window resolve (team rank 0 only).
@@ -451,20 +458,26 @@ __device__ __forceinline__ unsigned int seg_len_for(unsigned int live, unsigned 
 }
 
 // Screen candidates id0 .. id0+nc-1 of `src` (nc <= kTile) against
-// code[a, b), newest segment first, with the whole workgroup.  The segment
-// (64..1024 words, longer as fewer candidates stay live) is staged in LDS and
-// the next one is prefetched into registers meanwhile; the waves split the
-// (row of 64 candidates) x (chunk of 64 words) blocks.  After every segment
-// the conflicts are merged, killed candidates are marked in `src`, and the
-// survivors are compacted; the loop stops when none is left.  Every other
-// segment each live candidate is also looked up in `src` (overlapped with the
-// compute) to drop the ones another workgroup killed.  Returns the executed
-// checks (candidate slots x words).
+// code[a, b) with the whole workgroup.  Every workgroup that works on the
+// same tile shares `cursor`: each claims the next segment of the range,
+// newest first (the cursor counts words from b), so the workgroups of a tile
+// sweep the range together from the newest end.  A segment (64..4096 words,
+// longer as fewer candidates stay live) is staged in LDS while the next claim
+// is prefetched into registers; the waves split the (group of up to 4 rows of
+// 64 candidates) x (chunk of 64 words) blocks.  After every segment the
+// conflicts are merged, killed candidates are marked in `src`, candidates
+// that other workgroups killed meanwhile are dropped (their dead bits are
+// loaded during the compute), and the survivors are compacted.  A workgroup
+// stops when the range is exhausted or none of its candidates is live: it
+// only ever drops candidates that are dead, so a claimed segment is left
+// unscanned only when every candidate of the tile is dead.  Returns the
+// executed checks (candidate slots x words).
 __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint32_t *code, uint32_t id0,
                                           uint32_t nc, unsigned long long a, unsigned long long b,
-                                          uint32_t d) {
+                                          uint32_t d, unsigned long long *cursor) {
   TileLds &T = L.u.t;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const unsigned long long len = b > a ? b - a : 0;
   bool keep = false;
   uint32_t word = 0, id = 0;
   if (tid < (int)nc) {
@@ -476,36 +489,40 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
   unsigned int live = tile_compact(T, 0, keep, word, id);
   int cur = 0, buf = 0;
   unsigned long long checks = 0;
-  unsigned long long hi = b;
-  unsigned int nseg = 0;
+  if (live == 0 || len == 0) return 0;
+
+  // First claim: a short segment, so that the tile's first sweep is narrow.
   unsigned int slen = seg_len_for(live, 16);
+  // Claims alternate between two LDS slots: a slot is rewritten only after the
+  // barriers of the following segment, when every thread has read it.
+  int par = 0;
+  if (tid == 0) T.claim[0] = __hip_atomic_fetch_add(cursor, (unsigned long long)slen, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  unsigned long long off = T.claim[0];
   uint32_t nxt[kSegLoads];
-  if (live > 0 && hi > a) {
-    const unsigned long long lo_s = hi > a + slen ? hi - slen : a;
+  auto fetch = [&](unsigned long long o, unsigned int l) {
+    const unsigned long long hi = b - o, lo_s = hi > a + l ? hi - l : a;
 #pragma unroll
     for (int q = 0; q < kSegLoads; ++q) {
       const unsigned long long idx = lo_s + tid + (unsigned long long)q * kBlock;
-      nxt[q] = (unsigned int)(tid + q * kBlock) < slen ? code[idx < hi ? idx : hi - 1] : 0u;
+      nxt[q] = (unsigned int)(tid + q * kBlock) < l ? code[idx < hi ? idx : hi - 1] : 0u;
     }
-  }
-  while (live > 0 && hi > a) {
-    const unsigned long long lo_s = hi > a + slen ? hi - slen : a;
+  };
+  if (off < len) fetch(off, slen);
+  while (live > 0 && off < len) {
 #pragma unroll
-    for (int q = 0; q < kSegLoads; ++q)  // short ranges repeat the oldest word
+    for (int q = 0; q < kSegLoads; ++q)  // a clipped segment repeats its oldest word
       if ((unsigned int)(tid + q * kBlock) < slen) T.seg[buf][tid + q * kBlock] = nxt[q];
-    __syncthreads();
     const unsigned int next_len = seg_len_for(live, 64);
-    if (lo_s > a) {  // prefetch the next (older) segment
-      const unsigned long long lo2 = lo_s > a + next_len ? lo_s - next_len : a;
-#pragma unroll
-      for (int q = 0; q < kSegLoads; ++q) {
-        const unsigned long long idx = lo2 + tid + (unsigned long long)q * kBlock;
-        nxt[q] = (unsigned int)(tid + q * kBlock) < next_len ? code[idx < lo_s ? idx : lo_s - 1] : 0u;
-      }
-    }
-    const bool recheck = (nseg & 1) != 0;
+    par ^= 1;
+    if (tid == 0) T.claim[par] = __hip_atomic_fetch_add(cursor, (unsigned long long)next_len, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const unsigned long long next_off = T.claim[par];
+    if (next_off < len) fetch(next_off, next_len);  // in flight during the compute
     uint32_t deadw = 0;
-    if (recheck && tid < (int)live) deadw = src.dead_word(T.ci[cur][tid]);
+    if (tid < (int)live) deadw = src.dead_word(T.ci[cur][tid]);
     const unsigned int rows = (live + 63) / 64, chunks = slen / 64;
     const unsigned int groups = (rows + 3) / 4;
     if (lane < kRows) T.killw[wave][lane] = 0;
@@ -528,36 +545,30 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
       word = T.cw[cur][tid];
       id = T.ci[cur][tid];
       if (killed) src.kill(id);
-      keep = !killed && !(recheck && ((deadw >> (id & 31)) & 1));
+      keep = !killed && !((deadw >> (id & 31)) & 1);
     }
     live = tile_compact(T, cur ^ 1, keep, word, id);
     cur ^= 1;
     buf ^= 1;
-    hi = lo_s;
+    off = next_off;
     slen = next_len;
-    ++nseg;
   }
   return checks;
 }
 
-// Split of a 2-D screen (candidate tiles x a code range of `len` words) into
-// items for a team: enough range parts to give every workgroup an item, each
-// part a whole number of kPartQuantum words.
-struct Split {
-  unsigned long long tiles, parts, plen;
-};
-
-__device__ __forceinline__ Split make_split(unsigned long long ncand, unsigned long long len,
-                                            unsigned int team_size) {
-  Split sp;
-  sp.tiles = (ncand + kTile - 1) / kTile;
-  unsigned long long parts = (team_size + sp.tiles - 1) / sp.tiles;
-  const unsigned long long maxparts = (len + kPartQuantum - 1) / kPartQuantum;
-  if (parts > maxparts) parts = maxparts;
-  if (parts < 1) parts = 1;
-  sp.plen = ((len + parts - 1) / parts + kPartQuantum - 1) / kPartQuantum * kPartQuantum;
-  sp.parts = (len + sp.plen - 1) / sp.plen;
-  return sp;
+// Tiles of a 2-D screen (candidate tiles x one code range) for a team: with
+// fewer tiles than workgroups, workgroup r joins tile r mod tiles and the
+// workgroups of a tile share its range through the tile's cursor; otherwise
+// each workgroup takes tiles r, r + team_size, ... alone.
+template <typename F>
+__device__ __forceinline__ void for_my_tiles(const Lds &L, unsigned long long tiles, F &&f) {
+  const unsigned long long ts = L.team_size, r = L.team_rank;
+  if (tiles == 0) return;
+  if (tiles < ts) {
+    f(r % tiles);
+  } else {
+    for (unsigned long long t = r; t < tiles; t += ts) f(t);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -572,24 +583,14 @@ __device__ void resolve_window(Lds &L, const TeamWs &W) {
   ResolveLds &R = L.u.r;
   Ctl *ctl = W.ctl;
 
-  if (L.round == 0) {
+  if (L.round == 0 && L.mode == MODE_DEEP_ALL && L.lo > 0) {
+    // Every survivor was already scanned against code[0, lo) (survivor index
+    // = deep-list index): every fact is known.
+    for (unsigned int j = tid; j < s; j += kBlock)
+      L.st[j] = (ld_relaxed(&W.deep_fail[j >> 5]) >> (j & 31)) & 1 ? ST_FAIL : ST_PASS;
+    if (tid == 0 && s > 0) ctl->stat_rounds += 1;
+  } else if (L.round == 0) {
     for (unsigned int j = tid; j < s; j += kBlock) L.st[j] = L.lo == 0 ? ST_PASS : ST_UNKNOWN;
-    if (L.mode == MODE_DEEP_ALL && L.lo > 0 && s > 0) {
-      // Scan every survivor once; the resolve after that round has every fact.
-      for (unsigned int k = tid; k < s; k += kBlock) {
-        W.deep_word[k] = L.s1w[k];
-        W.deep_idx[k] = k;
-      }
-      for (unsigned int k = tid; k < (s + 31) / 32; k += kBlock) W.deep_fail[k] = 0;
-      if (tid == 0) {
-        L.ndeep = s;
-        ctl->ndeep = s;
-        ctl->action = ACT_DEEP;
-        ctl->stat_rounds += 1;
-      }
-      __syncthreads();
-      return;
-    }
   } else {
     for (unsigned int k = tid; k < L.ndeep; k += kBlock) {
       const uint32_t word = ld_relaxed(&W.deep_fail[k >> 5]);
@@ -623,14 +624,21 @@ __device__ void resolve_window(Lds &L, const TeamWs &W) {
       const int st = valid ? L.st[j] : ST_FAIL;
       bool killed = st == ST_FAIL;
       for (int J = 0; J < I; ++J) killed |= (R.adj[base + 64 * J + lane] & R.accm[J]) != 0;
-      unsigned long long alive = ballot(!killed);
+      const unsigned long long alive = ballot(!killed);
       const unsigned long long own = R.adj[base + 64 * I + lane];  // earlier neighbours in block
-      unsigned long long acc = 0;
-      while (alive) {
-        const int i = __builtin_ctzll(alive);
-        acc |= 1ull << i;
-        alive &= ~(1ull << i);
-        alive &= ~ballot((own >> i) & 1);
+      // Lexicographically first maximal independent set of the block, in
+      // synchronous rounds: an undecided survivor is rejected once an earlier
+      // neighbour is accepted, and accepted once every earlier neighbour is
+      // decided and none is accepted.  The first undecided survivor is always
+      // decided, so at most 64 rounds; dependency chains are short in practice.
+      unsigned long long acc = 0, und = alive;
+      while (und) {
+        const bool mine_und = (und >> lane) & 1;
+        const bool rej = mine_und && (own & acc) != 0;
+        const bool ok = mine_und && !rej && (own & und) == 0;
+        const unsigned long long newacc = ballot(ok);
+        und &= ~(newacc | ballot(rej));
+        acc |= newacc;
       }
       if (lane == 0) R.accm[I] = acc;
       const bool mine = (acc >> lane) & 1;
@@ -654,6 +662,7 @@ __device__ void resolve_window(Lds &L, const TeamWs &W) {
   const unsigned int tcount = L.tcount, ndeep = L.ndeep;
   if (ndeep > 0) {
     for (unsigned int k = tid; k < (ndeep + 31) / 32; k += kBlock) W.deep_fail[k] = 0;
+    if (tid < kDeepTiles) W.cur[kNearTiles + tid] = 0;
     if (tid == 0) {
       ctl->ndeep = ndeep;
       ctl->action = ACT_DEEP;
@@ -684,6 +693,9 @@ __device__ void resolve_window(Lds &L, const TeamWs &W) {
   if (next > kWMax) next = kWMax;
   next = (next + 63) & ~63ull;
   for (unsigned long long k = tid; k < (next + 31) / 32; k += kBlock) W.win_dead[k] = 0;
+  if (tid < kNearTiles) W.cur[tid] = 0;
+  if (tid < kDeepTiles) W.cur[kNearTiles + tid] = 0;
+  if (tid < kSMax / 32) W.deep_fail[tid] = 0;
 
   if (tid == 0) {
     ctl->stat_windows += 1;
@@ -743,17 +755,13 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
 
     // ---- A: near screen of [p0, pe0) against code[lo, m0) -----------------
     if (m0 > lo) {
-      const Split sp = make_split(nwin, m0 - lo, L.team_size);
       const Source src{&L.tab, L.n, L.ord, p0, nullptr, W.win_dead};
-      for (unsigned long long it = L.team_rank; it < sp.tiles * sp.parts; it += L.team_size) {
-        const unsigned long long part = it / sp.tiles, tile = it % sp.tiles;
-        const unsigned long long b = m0 - part * sp.plen;
-        const unsigned long long a = b > lo + sp.plen ? b - sp.plen : lo;
+      for_my_tiles(L, (nwin + kTile - 1) / kTile, [&](unsigned long long tile) {
         const unsigned long long id0 = tile * kTile;
         const uint32_t nc = (uint32_t)(nwin - id0 < (unsigned long long)kTile ? nwin - id0 : kTile);
-        const unsigned long long c = tile_screen(L, src, L.code, (uint32_t)id0, nc, a, b, d);
+        const unsigned long long c = tile_screen(L, src, L.code, (uint32_t)id0, nc, lo, m0, d, &W.cur[tile]);
         if (tid == 0) L.cnt_near += c;
-      }
+      });
     }
     team_barrier(L, P, P.spin_limit);
     charge(0);
@@ -840,8 +848,23 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
         if (lane == 0) atomicAdd(&L.cnt_pairs, 64ull * 64ull);
       }
     }
+    // Deep-scan-all policy: every survivor against code[0, lo) right away,
+    // from this workgroup's own copy of the survivor list (no barrier needed:
+    // the scan reads only the list and the committed code).
+    const bool deep_now = L.mode == MODE_DEEP_ALL && lo > 0 && L.s > 0;
+    if (deep_now) {
+      charge(1);
+      const Source src{&L.tab, L.n, L.ord, 0, L.s1w, W.deep_fail};
+      for_my_tiles(L, (L.s + kTile - 1) / kTile, [&](unsigned long long tile) {
+        const unsigned long long id0 = tile * kTile;
+        const uint32_t nc = (uint32_t)(L.s - id0 < (unsigned long long)kTile ? L.s - id0 : kTile);
+        const unsigned long long c =
+            tile_screen(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile]);
+        if (tid == 0) L.cnt_deep += c;
+      });
+    }
     team_barrier(L, P, P.spin_limit);
-    charge(1);
+    charge(deep_now ? 3 : 1);
 
     // ---- D / E rounds ------------------------------------------------------
     for (;;) {
@@ -859,17 +882,14 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
       // ---- E: deep scan of the listed survivors against code[0, lo) --------
       {
         const unsigned long long nd = L.ndeep;
-        const Split sp = make_split(nd, lo, L.team_size);
         const Source src{&L.tab, L.n, L.ord, 0, W.deep_word, W.deep_fail};
-        for (unsigned long long it = L.team_rank; it < sp.tiles * sp.parts; it += L.team_size) {
-          const unsigned long long part = it / sp.tiles, tile = it % sp.tiles;
-          const unsigned long long b = lo - part * sp.plen;
-          const unsigned long long a = b > sp.plen ? b - sp.plen : 0;
+        for_my_tiles(L, (nd + kTile - 1) / kTile, [&](unsigned long long tile) {
           const unsigned long long id0 = tile * kTile;
           const uint32_t nc = (uint32_t)(nd - id0 < (unsigned long long)kTile ? nd - id0 : kTile);
-          const unsigned long long c = tile_screen(L, src, L.code, (uint32_t)id0, nc, a, b, d);
+          const unsigned long long c =
+              tile_screen(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile]);
           if (tid == 0) L.cnt_deep += c;
-        }
+        });
       }
       if (tid == 0) L.round += 1;
       team_barrier(L, P, P.spin_limit);
@@ -952,16 +972,16 @@ __device__ __forceinline__ void persistent_body(Lds &L, const Params &P) {
       L.n = ld_sys(&J->n);
       L.d = ld_sys(&J->d);
       L.ord = ld_sys(&J->ord);
-      // Defaults by ordering (measured on the n=24 screens): graded orders have
-      // few window survivors killed only inside the window but many rejected
-      // deep in the code, so they screen the whole code up front; lex screens
-      // the newest 64K words and deep-scans every survivor once; Gray keeps
-      // its survivors' deep scans tentative.
+      // Defaults by ordering (measured on the n=24 screens): graded orders
+      // reject many candidates deep in the code, so they screen the whole code
+      // up front; lex and Gray screen the newest 16K words (where almost every
+      // rejected candidate meets its killer) and then deep-scan every survivor
+      // once.
       const bool graded = L.ord == GC_GRLEX || L.ord == GC_GREVLEX;
       const int mode = ld_sys(&J->mode);
-      L.mode = mode ? mode : (L.ord == GC_GRAY ? MODE_TENTATIVE : MODE_DEEP_ALL);
+      L.mode = mode ? mode : MODE_DEEP_ALL;
       const unsigned long long nd = ld_sys(&J->near_depth);
-      L.near_depth = nd ? nd : (graded ? ~0ull : (L.ord == GC_LEX ? 65536ull : kDefaultNear));
+      L.near_depth = nd ? nd : (graded ? ~0ull : kDefaultNear);
       const unsigned int tg = ld_sys(&J->target);
       L.target = tg ? (tg > (unsigned int)kSMax ? (unsigned int)kSMax : (tg < 16 ? 16 : tg)) : kDefaultTarget;
       L.code = ld_sys(&J->code);
@@ -986,6 +1006,10 @@ __device__ __forceinline__ void persistent_body(Lds &L, const Params &P) {
     for (unsigned long long k = (unsigned long long)L.team_rank * kBlock + tid; k < kWMax / 32;
          k += (unsigned long long)L.team_size * kBlock)
       W.win_dead[k] = 0;
+    for (unsigned long long k = (unsigned long long)L.team_rank * kBlock + tid; k < kCursors;
+         k += (unsigned long long)L.team_size * kBlock)
+      W.cur[k] = 0;
+    if (L.team_rank == 0 && tid < kSMax / 32) W.deep_fail[tid] = 0;
     team_barrier(L, P, P.spin_limit);
 
     if (L.d <= 1) emit_ordering(L, W);
@@ -1230,8 +1254,33 @@ int run_batch(Job *jobs, int njobs, int nteams, unsigned int grid_req, hipStream
   return GC_OK;
 }
 
+// Tunings chosen by greedy_code_tune, per device and instance.
+struct TuneKey {
+  int dev, n, d, ord;
+  bool operator<(const TuneKey &o) const {
+    if (dev != o.dev) return dev < o.dev;
+    if (n != o.n) return n < o.n;
+    if (d != o.d) return d < o.d;
+    return ord < o.ord;
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, gc_tuning> g_tuned;
+
+bool tuned_for(int n, int d, int ordering, gc_tuning *out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(TuneKey{dev, n, d, ordering});
+  if (it == g_tuned.end()) return false;
+  *out = it->second;
+  return true;
+}
+
 void fill_job(Job *J, int n, int d, int ordering, uint32_t *words, uint64_t capacity, uint64_t *count,
               const gc_tuning *tuning) {
+  gc_tuning remembered;
+  if (!tuning && tuned_for(n, d, ordering, &remembered)) tuning = &remembered;
   memset(J, 0, sizeof(*J));
   J->n = n;
   J->d = d;
@@ -1244,6 +1293,27 @@ void fill_job(Job *J, int n, int d, int ordering, uint32_t *words, uint64_t capa
     J->target = tuning->target_survivors;
     J->mode = (int)tuning->resolve_mode;
   }
+}
+
+int prepare_batch(const gc_job *jobs, int njobs, Job *J, int *order) {
+  for (int i = 0; i < njobs; ++i) {
+    const gc_job &g = jobs[i];
+    int rc = check_job_args(g.n, g.d, g.ordering);
+    if (rc) return fail(GC_EINVAL, "job %d: %s", i, g_error.c_str());
+    if (!g.d_words || ((uintptr_t)g.d_words & 15u) || g.capacity == 0)
+      return fail(GC_EINVAL, "job %d: d_words must be a 16-byte aligned device array", i);
+    fill_job(&J[i], g.n, g.d, g.ordering, g.d_words, g.capacity, g.d_count, nullptr);
+  }
+  // Teams claim jobs in queue order; the queue holds the jobs longest first
+  // (by the exhaustive-scan work bound 2^n * capacity), so that the largest
+  // codes do not start last and stretch the launch.
+  std::vector<double> est((size_t)njobs);
+  for (int i = 0; i < njobs; ++i) {
+    order[i] = i;
+    est[i] = std::ldexp((double)greedy_code_capacity(J[i].n, J[i].d), J[i].n);
+  }
+  std::stable_sort(order, order + njobs, [&](int a, int b) { return est[a] > est[b]; });
+  return GC_OK;
 }
 
 int job_result(const Job &J, uint64_t capacity) {
@@ -1361,24 +1431,9 @@ int greedy_code_batch(gc_job *jobs, int njobs, int teams, void *hip_stream, floa
   if (njobs < 0 || (!jobs && njobs > 0)) return fail(GC_EINVAL, "bad job array");
   if (teams == 0) teams = njobs >= 8 ? 8 : (njobs >= 4 ? 4 : (njobs >= 2 ? 2 : 1));
   std::vector<Job> J((size_t)njobs);
-  for (int i = 0; i < njobs; ++i) {
-    gc_job &g = jobs[i];
-    int rc = check_job_args(g.n, g.d, g.ordering);
-    if (rc) return fail(GC_EINVAL, "job %d: %s", i, g_error.c_str());
-    if (!g.d_words || ((uintptr_t)g.d_words & 15u) || g.capacity == 0)
-      return fail(GC_EINVAL, "job %d: d_words must be a 16-byte aligned device array", i);
-    fill_job(&J[i], g.n, g.d, g.ordering, g.d_words, g.capacity, g.d_count, nullptr);
-  }
-  // Teams claim jobs in queue order; the queue holds the jobs longest first
-  // (by the exhaustive-scan work bound 2^n * capacity), so that the largest
-  // codes do not start last and stretch the launch.
   std::vector<int> order((size_t)njobs);
-  std::vector<double> est((size_t)njobs);
-  for (int i = 0; i < njobs; ++i) {
-    order[i] = i;
-    est[i] = std::ldexp((double)greedy_code_capacity(J[i].n, J[i].d), J[i].n);
-  }
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return est[a] > est[b]; });
+  int rc0 = prepare_batch(jobs, njobs, J.data(), order.data());
+  if (rc0) return rc0;
   std::vector<Job> Q((size_t)njobs);
   for (int k = 0; k < njobs; ++k) Q[k] = J[order[k]];
   float ms = 0.f;
@@ -1393,6 +1448,99 @@ int greedy_code_batch(gc_job *jobs, int njobs, int teams, void *hip_stream, floa
   if (rc) return rc;
   for (int i = 0; i < njobs; ++i)
     if (jobs[i].status) return fail(jobs[i].status, "job %d failed with status %d", i, jobs[i].status);
+  return GC_OK;
+}
+
+
+int greedy_code_tune(int n, int d, int ordering, void *hip_stream, gc_tuning *best, float *best_ms) {
+  g_error.clear();
+  int rc = check_job_args(n, d, ordering);
+  if (rc) return rc;
+  if (!best) return fail(GC_EINVAL, "best is NULL");
+  memset(best, 0, sizeof(*best));
+  if (best_ms) *best_ms = 0.f;
+  if (d <= 1 || d > n) return GC_OK;  // the code is fixed without a search: nothing to tune
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipStream_t st = (hipStream_t)hip_stream;
+  const uint64_t cap = greedy_code_capacity(n, d);
+  // Candidates: near-screen depth (whole code, 64K, 16K or 4K newest words)
+  // with either deep-scan policy; then the fastest with a larger window.
+  std::vector<gc_tuning> cands = {
+      {~0ull, 0, 0, 0, 0},        {65536ull, 0, 0, 2, 0}, {65536ull, 0, 0, 1, 0},
+      {16384ull, 0, 0, 2, 0},     {16384ull, 0, 0, 1, 0}, {4096ull, 0, 0, 2, 0},
+  };
+  uint32_t *words = nullptr;
+  HIP_TRY(hipMallocAsync((void **)&words, (size_t)cap * sizeof(uint32_t), st));
+  std::vector<uint32_t> ref, cur;
+  uint64_t ref_m = 0;
+  float best_t = 0.f;
+  int best_i = -1;
+  auto run = [&](const gc_tuning &t, float *ms, std::vector<uint32_t> &out) -> int {
+    Job J;
+    fill_job(&J, n, d, ordering, words, cap, nullptr, &t);
+    int r = run_batch(&J, 1, 1, 0, st, ms, LaunchKind::kSingle);
+    if (r) return r;
+    r = job_result(J, cap);
+    if (r) return r;
+    out.resize(J.out_count);
+    hipError_t e = hipMemcpyAsync(out.data(), words, J.out_count * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(GC_EDEVICE, "copy of a tuning result failed: %s", hipGetErrorString(e));
+    return GC_OK;
+  };
+  float ms = 0.f;
+  rc = run(cands[0], &ms, ref);  // warm-up, also the reference output
+  ref_m = ref.size();
+  for (size_t i = 0; rc == GC_OK && i <= cands.size(); ++i) {
+    gc_tuning t;
+    if (i < cands.size()) {
+      t = cands[i];
+    } else {
+      t = cands[best_i];
+      t.target_survivors = 1000;
+    }
+    rc = run(t, &ms, cur);
+    if (rc) break;
+    if (cur.size() != ref_m || memcmp(cur.data(), ref.data(), ref_m * sizeof(uint32_t)) != 0) {
+      rc = fail(GC_EDEVICE, "tuning candidate %zu built a different code", i);
+      break;
+    }
+    if (best_i < 0 || ms < best_t) {
+      best_t = ms;
+      best_i = (int)(i < cands.size() ? i : cands.size());
+      *best = t;
+    }
+  }
+  const hipError_t ef = hipFreeAsync(words, st);
+  if (rc) return rc;
+  if (ef != hipSuccess) return fail(GC_EDEVICE, "hipFreeAsync failed: %s", hipGetErrorString(ef));
+  if (best_ms) *best_ms = best_t;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[TuneKey{dev, n, d, ordering}] = *best;
+  return GC_OK;
+}
+
+void greedy_code_tune_reset(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned.clear();
+}
+
+int greedy_code_batch_tune(gc_job *jobs, int njobs, void *hip_stream, int *best_teams, float *best_ms) {
+  g_error.clear();
+  if (!best_teams) return fail(GC_EINVAL, "best_teams is NULL");
+  *best_teams = 0;
+  float best_t = 0.f;
+  for (int teams = 1; teams <= kMaxTeams; teams *= 2) {
+    float ms = 0.f;
+    const int rc = greedy_code_batch(jobs, njobs, teams, hip_stream, &ms);
+    if (rc) return rc;
+    if (*best_teams == 0 || ms < best_t) {
+      best_t = ms;
+      *best_teams = teams;
+    }
+  }
+  if (best_ms) *best_ms = best_t;
   return GC_OK;
 }
 

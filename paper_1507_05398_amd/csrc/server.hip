@@ -161,6 +161,12 @@ int pump(gc_server *s) {
     J->capacity = greedy_code_capacity(t.n, t.d);
     J->count = nullptr;
     J->host_copy = reinterpret_cast<uint32_t *>(s->mirror_dev + off);
+    gc_tuning tu;
+    if (tuned_for(t.n, t.d, t.ord, &tu)) {
+      J->near_depth = tu.near_depth;
+      J->target = tu.target_survivors;
+      J->mode = (int)tu.resolve_mode;
+    }
     s->slot_ticket[t.slot] = id;
     s->inflight.insert(id);
     ++s->published;

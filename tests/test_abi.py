@@ -97,3 +97,34 @@ def test_server_create_fails_cleanly_without_device():
     h = ctypes.c_void_p()
     assert gc.load().gc_server_create(1 << 20, 8, ctypes.byref(h)) != gc.GC_OK
     assert gc.load().gc_server_create(1 << 20, 3, ctypes.byref(h)) == gc.GC_EINVAL
+
+
+def test_tuner_argument_validation_without_device():
+    lib = gc.load()
+    best, ms = gc._native.GcTuning(), ctypes.c_float()
+    for args in [(0, 3, 0), (5, 0, 0), (5, 3, 7)]:
+        assert lib.greedy_code_tune(*args, None, ctypes.byref(best), ctypes.byref(ms)) == gc.GC_EINVAL
+    assert lib.greedy_code_tune(5, 3, 0, None, None, None) == gc.GC_EINVAL
+    # Degenerate d: the code needs no search, so there is nothing to tune.
+    best.near_depth = 99
+    assert lib.greedy_code_tune(5, 1, 0, None, ctypes.byref(best), ctypes.byref(ms)) == gc.GC_OK
+    assert best.near_depth == 0 and ms.value == 0.0
+    assert lib.greedy_code_tune(5, 6, 2, None, ctypes.byref(best), None) == gc.GC_OK
+    lib.greedy_code_tune_reset()
+    jobs = (gc._native.GcJob * 1)()
+    assert lib.greedy_code_batch_tune(jobs, 1, None, None, None) == gc.GC_EINVAL
+
+
+def test_batch_graph_argument_validation_without_device():
+    lib = gc.load()
+    h = ctypes.c_void_p()
+    jobs = (gc._native.GcJob * 1)()
+    assert lib.gc_batch_graph_create(jobs, 0, 1, ctypes.byref(h)) == gc.GC_EINVAL
+    assert lib.gc_batch_graph_create(None, 1, 1, ctypes.byref(h)) == gc.GC_EINVAL
+    assert lib.gc_batch_graph_create(jobs, 1, 3, ctypes.byref(h)) == gc.GC_EINVAL
+    jobs[0].n, jobs[0].d, jobs[0].ordering, jobs[0].d_words, jobs[0].capacity = 5, 0, 0, 64, 16
+    assert lib.gc_batch_graph_create(jobs, 1, 1, ctypes.byref(h)) == gc.GC_EINVAL
+    assert lib.gc_batch_graph_create(jobs, 1, 1, None) == gc.GC_EINVAL
+    assert lib.gc_batch_graph_launch(None, None) == gc.GC_EINVAL
+    assert lib.gc_batch_graph_results(None, jobs) == gc.GC_EINVAL
+    assert lib.gc_batch_graph_destroy(None) == gc.GC_OK

@@ -153,3 +153,30 @@ def test_server_relaunches_after_idle():
         wait_all(srv, [t2])
         assert np.array_equal(srv.fetch(t), ref(15, 3, "lex"))
         assert np.array_equal(srv.fetch(t2), ref(13, 4, "gray"))
+
+
+def test_batch_graph_replays_match_oracle():
+    """A captured batch replayed three times, with eager work and cleared
+    outputs between the replays: every replay rebuilds every code."""
+    import torch
+    ords = ["lex", "gray", "grlex", "grevlex"]
+    insts = [(10 + (i % 7), 3 + (i % 5), ords[i % 4]) for i in range(20)]
+    refs = [oracle.greedy_ball(n, d, oracle.ORDERINGS[o])[0] for n, d, o in insts]
+    plan = gc.BatchPlan(insts)
+    print(f"[graph] capture {len(insts)} jobs", flush=True)
+    with plan.graph() as g:
+        for rep in range(3):
+            for w, c in plan.bufs:
+                w.fill_(-1)
+                c.zero_()
+            words, _ = gc.device_code(12, 3, "gray")   # eager work between replays
+            np.testing.assert_array_equal(words.cpu().numpy().view(np.uint32),
+                                          oracle.greedy_ball(12, 3, oracle.ORDERINGS["gray"])[0])
+            torch.cuda.synchronize()
+            print(f"[graph] replay {rep}", flush=True)
+            g.launch()
+            g.wait()
+            for (n, d, o), ref, t, (w, c), inf in zip(insts, refs, plan.results(), plan.bufs, plan.info()):
+                assert inf["status"] == gc.GC_OK and inf["count"] == len(ref)
+                assert int(c.item()) == len(ref)
+                np.testing.assert_array_equal(t.cpu().numpy().view(np.uint32), ref)
