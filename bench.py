@@ -196,6 +196,21 @@ def bench_batched(gc, torch, steps, warmup, log):
         if len(t) != m or digest_of(t) != dig:
             raise SystemExit(f"BATCH MISMATCH job {i} ({key})")
 
+    # The same batch captured once into a HIP graph and replayed.
+    gwalls = []
+    with plan.graph() as g:
+        g.launch(stream)
+        g.wait()
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            g.launch(stream)
+            g.wait()
+            gwalls.append(time.perf_counter() - t0)
+    for i, t in enumerate(plan.results()):
+        key, m, dig, _, _ = expected[i]
+        if len(t) != m or digest_of(t) != dig:
+            raise SystemExit(f"GRAPH MISMATCH job {i} ({key})")
+
     def plain(record):
         for i, ((n, d, o), (w, c)) in enumerate(zip(insts, plan.bufs)):
             st = gc.greedy_code_device_ex(n, d, o, w, c, stream=stream)
@@ -221,6 +236,7 @@ def bench_batched(gc, torch, steps, warmup, log):
             "batched_kernel_ms": round(sorted(kms)[len(kms) // 2], 3),
             "plain_codes_per_s": round(len(insts) / tp, 2), "plain_ms": round(tp * 1e3, 3),
             "speedup": round(tp / tb, 3),
+            "graph_codes_per_s": round(len(insts) / sorted(gwalls)[len(gwalls) // 2], 2),
             "batched_gchecks_per_s": round(w_ee / tb / 1e9, 3)}
 
 

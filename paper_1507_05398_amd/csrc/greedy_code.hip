@@ -75,7 +75,8 @@ constexpr int kAdjWords = 64 * kNb * (kNb + 1) / 2;   // lower-triangular block 
 constexpr unsigned long long kWMin = 256;
 constexpr unsigned long long kWMax = 1ull << 18;
 constexpr int kWordsPerThread = (int)(kWMax / 32 / kBlock);  // window mask words per thread
-constexpr unsigned int kDefaultTarget = 768;
+constexpr unsigned int kDefaultTarget = 768;         // graded orderings
+constexpr unsigned int kDefaultTargetLinear = 1000;  // lex and Gray (window cut at kSMax survivors)
 constexpr unsigned long long kDefaultNear = 16384;
 constexpr unsigned int kDefaultSpin = 1u << 25;
 
@@ -135,6 +136,8 @@ struct TileLds {
   unsigned long long killw[kWaves][kRows];
   unsigned int wcnt[kWaves];
   unsigned long long claim[2];         // offsets (from the newest end) of claimed segments, by parity
+  uint32_t dloc[32];                   // kills found by this workgroup (the tile's dead-bit words)
+  uint32_t dseen[32];                  // the tile's published dead bits, as last loaded
 };
 
 // In-window resolve (team rank 0 only).
@@ -383,11 +386,6 @@ struct Source {
   __device__ uint32_t word(uint32_t id) const {
     return words ? words[id] : position_word(*tab, n, ord, p0 + id);
   }
-  __device__ bool is_dead(uint32_t id) const { return (ld_relaxed(&dead[id >> 5]) >> (id & 31)) & 1; }
-  __device__ uint32_t dead_word(uint32_t id) const { return ld_relaxed(&dead[id >> 5]); }
-  __device__ void kill(uint32_t id) const {
-    __hip_atomic_fetch_or(&dead[id >> 5], 1u << (id & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
 };
 
 // Workgroup compaction: thread t offers entry t (keep, word, id); kept
@@ -457,47 +455,53 @@ __device__ __forceinline__ unsigned int seg_len_for(unsigned int live, unsigned 
   return 64u * (chunks ? chunks : 1u);
 }
 
-// Screen candidates id0 .. id0+nc-1 of `src` (nc <= kTile) against
-// code[a, b) with the whole workgroup.  Every workgroup that works on the
-// same tile shares `cursor`: each claims the next segment of the range,
-// newest first (the cursor counts words from b), so the workgroups of a tile
-// sweep the range together from the newest end.  A segment (64..4096 words,
-// longer as fewer candidates stay live) is staged in LDS while the next claim
-// is prefetched into registers; the waves split the (group of up to 4 rows of
-// 64 candidates) x (chunk of 64 words) blocks.  After every segment the
-// conflicts are merged, killed candidates are marked in `src`, candidates
-// that other workgroups killed meanwhile are dropped (their dead bits are
-// loaded during the compute), and the survivors are compacted.  A workgroup
-// stops when the range is exhausted or none of its candidates is live: it
-// only ever drops candidates that are dead, so a claimed segment is left
-// unscanned only when every candidate of the tile is dead.  Returns the
-// executed checks (candidate slots x words).
+// Screen candidates id0 .. id0+nc-1 of `src` (nc <= kTile, id0 a multiple of
+// kTile) against code[a, b) with the whole workgroup, one of `members`
+// workgroups that share this tile.  The members share `cursor`: each claims
+// the next segment of the range, newest first (the cursor counts words from
+// b), so together they sweep the range from the newest end.  A segment is at
+// most 1/(2 members) of the range (so the last claims do not leave a few
+// members with long tails) and otherwise 64..4096 words, longer as fewer
+// candidates stay live; it is staged in LDS while the next claim is prefetched
+// into registers, and the waves split the (group of up to 4 rows of 64
+// candidates) x (chunk of 64 words) blocks.  After every segment the kills
+// are gathered into the tile's 32 dead-bit words in LDS and published with at
+// most 32 atomic ORs; the same 32 words, loaded during the compute, drop the
+// candidates that other members killed; the survivors are compacted.  A
+// member stops when the range is exhausted or none of its candidates is live:
+// it only drops dead candidates, so a claimed segment is left unscanned only
+// when every candidate of the tile is dead.  The tile's dead bits are clear
+// when a screen starts.  Returns the executed checks (candidate slots x
+// words).
 __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint32_t *code, uint32_t id0,
                                           uint32_t nc, unsigned long long a, unsigned long long b,
-                                          uint32_t d, unsigned long long *cursor) {
+                                          uint32_t d, unsigned long long *cursor, unsigned int members) {
   TileLds &T = L.u.t;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const unsigned long long len = b > a ? b - a : 0;
+  if (len == 0 || nc == 0) return 0;
+  uint32_t *dead = src.dead + (id0 >> 5);  // the tile's 32 dead-bit words
+  const unsigned long long share = (len / (2ull * members) + 63) & ~63ull;
+  const unsigned int cap = share < 64 ? 64u : (share > (unsigned long long)kSegMax ? (unsigned)kSegMax : (unsigned)share);
   bool keep = false;
   uint32_t word = 0, id = 0;
   if (tid < (int)nc) {
     id = id0 + tid;
-    const uint32_t deadw = src.dead_word(id);  // both loads in flight together
     word = src.word(id);
-    keep = !((deadw >> (id & 31)) & 1);
+    keep = true;
   }
   unsigned int live = tile_compact(T, 0, keep, word, id);
   int cur = 0, buf = 0;
   unsigned long long checks = 0;
-  if (live == 0 || len == 0) return 0;
 
   // First claim: a short segment, so that the tile's first sweep is narrow.
-  unsigned int slen = seg_len_for(live, 16);
+  unsigned int slen = umin(seg_len_for(live, 16), cap);
   // Claims alternate between two LDS slots: a slot is rewritten only after the
   // barriers of the following segment, when every thread has read it.
   int par = 0;
   if (tid == 0) T.claim[0] = __hip_atomic_fetch_add(cursor, (unsigned long long)slen, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
+  if (tid < 32) T.dloc[tid] = 0;
   __syncthreads();
   unsigned long long off = T.claim[0];
   uint32_t nxt[kSegLoads];
@@ -514,15 +518,15 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
 #pragma unroll
     for (int q = 0; q < kSegLoads; ++q)  // a clipped segment repeats its oldest word
       if ((unsigned int)(tid + q * kBlock) < slen) T.seg[buf][tid + q * kBlock] = nxt[q];
-    const unsigned int next_len = seg_len_for(live, 64);
+    const unsigned int next_len = umin(seg_len_for(live, 64), cap);
     par ^= 1;
     if (tid == 0) T.claim[par] = __hip_atomic_fetch_add(cursor, (unsigned long long)next_len, __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const unsigned long long next_off = T.claim[par];
     if (next_off < len) fetch(next_off, next_len);  // in flight during the compute
-    uint32_t deadw = 0;
-    if (tid < (int)live) deadw = src.dead_word(T.ci[cur][tid]);
+    uint32_t seen = 0;
+    if (tid < 32) seen = ld_relaxed(&dead[tid]);  // kills published by the other members
     const unsigned int rows = (live + 63) / 64, chunks = slen / 64;
     const unsigned int groups = (rows + 3) / 4;
     if (lane < kRows) T.killw[wave][lane] = 0;
@@ -535,18 +539,24 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
       else rows_chunk<1>(T, cur, buf, row0, chunk, live, d);
     }
     checks += 64ull * rows * slen;
+    if (tid < 32) T.dseen[tid] = seen;
     __syncthreads();
-    keep = false;
+    bool killed = false;
     if (tid < (int)live) {
       unsigned long long k = 0;
 #pragma unroll
       for (int w = 0; w < kWaves; ++w) k |= T.killw[w][tid >> 6];
-      const bool killed = (k >> (tid & 63)) & 1;
+      killed = (k >> (tid & 63)) & 1;
       word = T.cw[cur][tid];
       id = T.ci[cur][tid];
-      if (killed) src.kill(id);
-      keep = !killed && !((deadw >> (id & 31)) & 1);
+      if (killed) atomicOr(&T.dloc[(id - id0) >> 5], 1u << (id & 31));
     }
+    __syncthreads();
+    if (tid < 32) {  // publish this segment's kills, one atomic per dead-bit word
+      const uint32_t mine = T.dloc[tid];
+      if (mine & ~T.dseen[tid]) __hip_atomic_fetch_or(&dead[tid], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    keep = tid < (int)live && !killed && !((T.dseen[(id - id0) >> 5] >> (id & 31)) & 1);
     live = tile_compact(T, cur ^ 1, keep, word, id);
     cur ^= 1;
     buf ^= 1;
@@ -565,9 +575,10 @@ __device__ __forceinline__ void for_my_tiles(const Lds &L, unsigned long long ti
   const unsigned long long ts = L.team_size, r = L.team_rank;
   if (tiles == 0) return;
   if (tiles < ts) {
-    f(r % tiles);
+    const unsigned long long t = r % tiles;
+    f(t, (unsigned int)((ts - t + tiles - 1) / tiles));
   } else {
-    for (unsigned long long t = r; t < tiles; t += ts) f(t);
+    for (unsigned long long t = r; t < tiles; t += ts) f(t, 1u);
   }
 }
 
@@ -756,10 +767,11 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
     // ---- A: near screen of [p0, pe0) against code[lo, m0) -----------------
     if (m0 > lo) {
       const Source src{&L.tab, L.n, L.ord, p0, nullptr, W.win_dead};
-      for_my_tiles(L, (nwin + kTile - 1) / kTile, [&](unsigned long long tile) {
+      for_my_tiles(L, (nwin + kTile - 1) / kTile, [&](unsigned long long tile, unsigned int members) {
         const unsigned long long id0 = tile * kTile;
         const uint32_t nc = (uint32_t)(nwin - id0 < (unsigned long long)kTile ? nwin - id0 : kTile);
-        const unsigned long long c = tile_screen(L, src, L.code, (uint32_t)id0, nc, lo, m0, d, &W.cur[tile]);
+        const unsigned long long c =
+            tile_screen(L, src, L.code, (uint32_t)id0, nc, lo, m0, d, &W.cur[tile], members);
         if (tid == 0) L.cnt_near += c;
       });
     }
@@ -855,11 +867,11 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
     if (deep_now) {
       charge(1);
       const Source src{&L.tab, L.n, L.ord, 0, L.s1w, W.deep_fail};
-      for_my_tiles(L, (L.s + kTile - 1) / kTile, [&](unsigned long long tile) {
+      for_my_tiles(L, (L.s + kTile - 1) / kTile, [&](unsigned long long tile, unsigned int members) {
         const unsigned long long id0 = tile * kTile;
         const uint32_t nc = (uint32_t)(L.s - id0 < (unsigned long long)kTile ? L.s - id0 : kTile);
         const unsigned long long c =
-            tile_screen(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile]);
+            tile_screen(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members);
         if (tid == 0) L.cnt_deep += c;
       });
     }
@@ -883,11 +895,11 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
       {
         const unsigned long long nd = L.ndeep;
         const Source src{&L.tab, L.n, L.ord, 0, W.deep_word, W.deep_fail};
-        for_my_tiles(L, (nd + kTile - 1) / kTile, [&](unsigned long long tile) {
+        for_my_tiles(L, (nd + kTile - 1) / kTile, [&](unsigned long long tile, unsigned int members) {
           const unsigned long long id0 = tile * kTile;
           const uint32_t nc = (uint32_t)(nd - id0 < (unsigned long long)kTile ? nd - id0 : kTile);
           const unsigned long long c =
-              tile_screen(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile]);
+              tile_screen(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members);
           if (tid == 0) L.cnt_deep += c;
         });
       }
@@ -983,7 +995,8 @@ __device__ __forceinline__ void persistent_body(Lds &L, const Params &P) {
       const unsigned long long nd = ld_sys(&J->near_depth);
       L.near_depth = nd ? nd : (graded ? ~0ull : kDefaultNear);
       const unsigned int tg = ld_sys(&J->target);
-      L.target = tg ? (tg > (unsigned int)kSMax ? (unsigned int)kSMax : (tg < 16 ? 16 : tg)) : kDefaultTarget;
+      L.target = tg ? (tg > (unsigned int)kSMax ? (unsigned int)kSMax : (tg < 16 ? 16 : tg))
+                    : (graded ? kDefaultTarget : kDefaultTargetLinear);
       L.code = ld_sys(&J->code);
       L.capacity = ld_sys(&J->capacity);
       L.total = 1ull << L.n;
