@@ -135,9 +135,10 @@ typedef struct gc_job {
 
 /* Build many codes (batched workload; no paper counterpart: the paper
  * builds one code per run) in one persistent launch on `hip_stream`: the
- * workgroups form `teams` teams (1, 2, 4 or 8; 0 = choose by job count) by
- * XCD and each team pulls the next job from a device queue, so codes of
- * uneven size share the GPU.  Every code is bit-identical to what
+ * workgroups form `teams` teams by XCD (1, 2, 4 or 8; 0 = 4 teams from 4
+ * jobs up, fewer below) and each team pulls the next job from a device
+ * queue that holds the jobs longest first, so codes of uneven size share the
+ * GPU.  Every code is bit-identical to what
  * greedy_code_device returns for it.  Returns GC_OK when every job succeeded,
  * otherwise the first failing job's code (each job's status is set).
  * kernel_ms (may be NULL) receives the device time of the launch. */

@@ -54,7 +54,7 @@ int gc_batch_graph_create(const gc_job *jobs, int njobs, int teams, gc_batch_gra
   if (!out) return fail(GC_EINVAL, "out is NULL");
   *out = nullptr;
   if (njobs <= 0 || !jobs) return fail(GC_EINVAL, "a graph needs at least one job");
-  if (teams == 0) teams = njobs >= 8 ? 8 : (njobs >= 4 ? 4 : (njobs >= 2 ? 2 : 1));
+  if (teams == 0) teams = njobs >= 4 ? 4 : (njobs >= 2 ? 2 : 1);
   if (teams != 1 && teams != 2 && teams != 4 && teams != 8)
     return fail(GC_EINVAL, "teams must be 1, 2, 4 or 8 (got %d)", teams);
   std::vector<Job> J((size_t)njobs);
