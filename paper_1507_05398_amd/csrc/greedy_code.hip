@@ -78,7 +78,14 @@ constexpr int kWordsPerThread = (int)(kWMax / 32 / kBlock);  // window mask word
 constexpr unsigned int kDefaultTarget = 768;         // graded orderings
 constexpr unsigned int kDefaultTargetLinear = 1000;  // lex and Gray (window cut at kSMax survivors)
 constexpr unsigned long long kDefaultNear = 16384;
-constexpr unsigned long long kDefaultNearGray = 4096;
+constexpr unsigned long long kDefaultNearGray = 8192;
+// Work per segment after the first, in (group of 4 rows) x (64 words) blocks
+// (measured on the n=24..28 screens): short segments for a near screen over
+// the newest words, where candidates die early and kills should spread
+// fast; longer ones for the deep scan and for a near screen over the whole
+// code, where most candidates survive long ranges.
+constexpr unsigned int kNearBlocks = 16;
+constexpr unsigned int kDeepBlocks = 32;
 constexpr unsigned int kDefaultSpin = 1u << 25;
 
 enum : int { ST_UNKNOWN = 0, ST_PASS = 1, ST_FAIL = 2 };
@@ -476,7 +483,8 @@ __device__ __forceinline__ unsigned int seg_len_for(unsigned int live, unsigned 
 // words).
 __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint32_t *code, uint32_t id0,
                                           uint32_t nc, unsigned long long a, unsigned long long b,
-                                          uint32_t d, unsigned long long *cursor, unsigned int members) {
+                                          uint32_t d, unsigned long long *cursor, unsigned int members,
+                                          unsigned int blocks) {
   TileLds &T = L.u.t;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const unsigned long long len = b > a ? b - a : 0;
@@ -519,7 +527,7 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
 #pragma unroll
     for (int q = 0; q < kSegLoads; ++q)  // a clipped segment repeats its oldest word
       if ((unsigned int)(tid + q * kBlock) < slen) T.seg[buf][tid + q * kBlock] = nxt[q];
-    const unsigned int next_len = umin(seg_len_for(live, 64), cap);
+    const unsigned int next_len = umin(seg_len_for(live, blocks), cap);
     par ^= 1;
     if (tid == 0) T.claim[par] = __hip_atomic_fetch_add(cursor, (unsigned long long)next_len, __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_AGENT);
@@ -772,7 +780,8 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
         const unsigned long long id0 = tile * kTile;
         const uint32_t nc = (uint32_t)(nwin - id0 < (unsigned long long)kTile ? nwin - id0 : kTile);
         const unsigned long long c =
-            tile_screen(L, src, L.code, (uint32_t)id0, nc, lo, m0, d, &W.cur[tile], members);
+            tile_screen(L, src, L.code, (uint32_t)id0, nc, lo, m0, d, &W.cur[tile], members,
+                        lo == 0 ? kDeepBlocks : kNearBlocks);
         if (tid == 0) L.cnt_near += c;
       });
     }
@@ -872,7 +881,8 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
         const unsigned long long id0 = tile * kTile;
         const uint32_t nc = (uint32_t)(L.s - id0 < (unsigned long long)kTile ? L.s - id0 : kTile);
         const unsigned long long c =
-            tile_screen(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members);
+            tile_screen(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members,
+                        kDeepBlocks);
         if (tid == 0) L.cnt_deep += c;
       });
     }
@@ -900,7 +910,8 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
           const unsigned long long id0 = tile * kTile;
           const uint32_t nc = (uint32_t)(nd - id0 < (unsigned long long)kTile ? nd - id0 : kTile);
           const unsigned long long c =
-              tile_screen(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members);
+              tile_screen(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members,
+                        kDeepBlocks);
           if (tid == 0) L.cnt_deep += c;
         });
       }
@@ -988,7 +999,7 @@ __device__ __forceinline__ void persistent_body(Lds &L, const Params &P) {
       // Defaults by ordering (measured on the n=24..28 screens): graded
       // orders reject many candidates deep in the code, so they screen the
       // whole code up front; lex screens the newest 16K words and Gray the
-      // newest 4K (where almost every rejected candidate meets its killer),
+      // newest 8K (where almost every rejected candidate meets its killer),
       // and both then deep-scan every survivor once.
       const bool graded = L.ord == GC_GRLEX || L.ord == GC_GREVLEX;
       const int mode = ld_sys(&J->mode);
