@@ -536,12 +536,15 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
     if (next_off < len) fetch(next_off, next_len);  // in flight during the compute
     uint32_t seen = 0;
     if (tid < 32) seen = ld_relaxed(&dead[tid]);  // kills published by the other members
+    // Rows go to ceil(rows / 4) groups of balanced sizes (they differ by at
+    // most one), and consecutive blocks share a group, so that the waves'
+    // shares of a segment are close to equal.
     const unsigned int rows = (live + 63) / 64, chunks = slen / 64;
     const unsigned int groups = (rows + 3) / 4;
     if (lane < kRows) T.killw[wave][lane] = 0;
     for (unsigned int blk = wave; blk < groups * chunks; blk += kWaves) {
-      const unsigned int g = blk % groups, chunk = blk / groups;
-      const unsigned int row0 = 4 * g, rg = rows - row0 < 4 ? rows - row0 : 4;
+      const unsigned int g = blk / chunks, chunk = blk % chunks;
+      const unsigned int row0 = g * rows / groups, rg = (g + 1) * rows / groups - row0;
       if (rg == 4) rows_chunk<4>(T, cur, buf, row0, chunk, live, d);
       else if (rg == 3) rows_chunk<3>(T, cur, buf, row0, chunk, live, d);
       else if (rg == 2) rows_chunk<2>(T, cur, buf, row0, chunk, live, d);
