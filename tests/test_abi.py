@@ -128,3 +128,9 @@ def test_batch_graph_argument_validation_without_device():
     assert lib.gc_batch_graph_launch(None, None) == gc.GC_EINVAL
     assert lib.gc_batch_graph_results(None, jobs) == gc.GC_EINVAL
     assert lib.gc_batch_graph_destroy(None) == gc.GC_OK
+
+
+def test_empty_batch_is_a_no_op():
+    lib = gc.load()
+    ms = ctypes.c_float(-1.0)
+    assert lib.greedy_code_batch(None, 0, 0, None, ctypes.byref(ms)) == gc.GC_OK

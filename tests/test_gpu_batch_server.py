@@ -180,3 +180,29 @@ def test_batch_graph_replays_match_oracle():
                 assert inf["status"] == gc.GC_OK and inf["count"] == len(ref)
                 assert int(c.item()) == len(ref)
                 np.testing.assert_array_equal(t.cpu().numpy().view(np.uint32), ref)
+
+
+def test_served_workload_sample_matches_oracle():
+    """The served workload (seeded Poisson stream: n in [10, 26] skewed small,
+    d in [3, 10], random ordering): its first 400 jobs with n <= 20, all
+    submitted at once to an 8-team server whose 512 KiB arena holds only part
+    of their worst-case codes (admission by memory binds: jobs wait until
+    finished ones are released); every result is compared with the oracle."""
+    jobs = [j for j in workloads.served_jobs(seed=1507, count=2000, rate=1.0) if j[1] <= 20][:400]
+    log(f"[served] {len(jobs)} jobs")
+    got = {}
+    waited = 0
+    with gc.Server(arena_bytes=512 << 10, teams=8) as srv:
+        open_tickets = {srv.submit(n, d, o): i for i, (_, n, d, o) in enumerate(jobs)}
+        deadline = time.time() + 90
+        while open_tickets and time.time() < deadline:
+            for tk in list(open_tickets):
+                st, _ = srv.poll(tk)
+                waited += st == gc.GC_JOB_WAITING
+                if st >= gc.GC_JOB_DONE:
+                    got[open_tickets.pop(tk)] = srv.fetch(tk)
+                    srv.release(tk)
+        assert not open_tickets, f"{len(open_tickets)} jobs unfinished"
+    assert waited > 0  # some jobs did wait for memory
+    for i, (_, n, d, o) in enumerate(jobs):
+        np.testing.assert_array_equal(got[i], ref(n, d, o))
