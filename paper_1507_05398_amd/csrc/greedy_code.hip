@@ -536,11 +536,13 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
     if (next_off < len) fetch(next_off, next_len);  // in flight during the compute
     uint32_t seen = 0;
     if (tid < 32) seen = ld_relaxed(&dead[tid]);  // kills published by the other members
-    // Rows go to ceil(rows / 4) groups of balanced sizes (they differ by at
-    // most one), and consecutive blocks share a group, so that the waves'
-    // shares of a segment are close to equal.
+    // Rows go to 1, 2 or 4 groups of balanced sizes (they differ by at most
+    // one; 9..12 rows make 4 groups of 2-3 rather than 3 groups of 4, so that
+    // the block count of a segment, groups x chunks, stays a multiple of the
+    // 16 waves), and consecutive blocks share a group: every wave gets the
+    // same share of the segment.
     const unsigned int rows = (live + 63) / 64, chunks = slen / 64;
-    const unsigned int groups = (rows + 3) / 4;
+    const unsigned int groups = rows > 8 ? 4u : (rows > 4 ? 2u : 1u);
     if (lane < kRows) T.killw[wave][lane] = 0;
     for (unsigned int blk = wave; blk < groups * chunks; blk += kWaves) {
       const unsigned int g = blk / chunks, chunk = blk % chunks;
