@@ -398,11 +398,15 @@ struct Source {
 
 // Workgroup compaction: thread t offers entry t (keep, word, id); kept
 // entries go densely and in order to buffer dst.  Returns the count.
-__device__ unsigned int tile_compact(TileLds &T, int dst, bool keep, uint32_t word, uint32_t id) {
+// `between` runs after the first barrier (everything written to LDS before
+// the call is visible to it).
+template <typename F>
+__device__ unsigned int tile_compact(TileLds &T, int dst, bool keep, uint32_t word, uint32_t id, F &&between) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const unsigned long long m = ballot(keep);
   if (lane == 0) T.wcnt[wave] = (unsigned int)__builtin_popcountll(m);
   __syncthreads();
+  between();
   unsigned int base = 0, total = 0;
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) {
@@ -416,6 +420,10 @@ __device__ unsigned int tile_compact(TileLds &T, int dst, bool keep, uint32_t wo
   }
   __syncthreads();
   return total;
+}
+
+__device__ __forceinline__ unsigned int tile_compact(TileLds &T, int dst, bool keep, uint32_t word, uint32_t id) {
+  return tile_compact(T, dst, keep, word, id, [] {});
 }
 
 // RG rows of 64 live candidates (rows row0 .. row0+RG-1) against the 64
@@ -565,13 +573,15 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
       id = T.ci[cur][tid];
       if (killed) atomicOr(&T.dloc[(id - id0) >> 5], 1u << (id & 31));
     }
-    __syncthreads();
-    if (tid < 32) {  // publish this segment's kills, one atomic per dead-bit word
-      const uint32_t mine = T.dloc[tid];
-      if (mine & ~T.dseen[tid]) __hip_atomic_fetch_or(&dead[tid], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
     keep = tid < (int)live && !killed && !((T.dseen[(id - id0) >> 5] >> (id & 31)) & 1);
-    live = tile_compact(T, cur ^ 1, keep, word, id);
+    // The kills are published after the compaction's first barrier, which
+    // also completes the gathering in dloc.
+    live = tile_compact(T, cur ^ 1, keep, word, id, [&] {
+      if (tid < 32) {  // one atomic per dead-bit word
+        const uint32_t mine = T.dloc[tid];
+        if (mine & ~T.dseen[tid]) __hip_atomic_fetch_or(&dead[tid], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    });
     cur ^= 1;
     buf ^= 1;
     off = next_off;
