@@ -141,7 +141,7 @@ struct TileLds {
   alignas(16) uint32_t seg[2][kSegMax];
   uint32_t cw[2][kTile];
   uint32_t ci[2][kTile];
-  unsigned long long killw[kWaves][kRows];
+  unsigned long long killw[kRows];     // kill mask of each row of 64 live candidates
   unsigned int wcnt[kWaves];
   unsigned long long claim[2];         // offsets (from the newest end) of claimed segments, by parity
   uint32_t dloc[32];                   // kills found by this workgroup (the tile's dead-bit words)
@@ -192,6 +192,14 @@ __device__ __forceinline__ uint32_t umin3(uint32_t a, uint32_t b, uint32_t c) {
 __device__ __forceinline__ uint32_t dist(uint32_t a, uint32_t b) { return __builtin_popcount(a ^ b); }
 
 __device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
+
+// Load through a pointer known to address global memory.  A generic (flat)
+// load also counts on the LDS counter until its data returns, so every LDS
+// wait issued meanwhile would wait for the global access as well.
+template <typename T>
+__device__ __forceinline__ T gload(const T *p) {
+  return *(const __attribute__((address_space(1))) T *)p;
+}
 
 __device__ __forceinline__ unsigned long long lanemask_lt() {
   const unsigned int l = __lane_id();
@@ -429,32 +437,41 @@ __device__ __forceinline__ unsigned int tile_compact(TileLds &T, int dst, bool k
 // RG rows of 64 live candidates (rows row0 .. row0+RG-1) against the 64
 // staged words of one chunk: every word broadcast from LDS serves RG
 // candidates per lane, which keeps the LDS read rate below the VALU rate.
-// Merges the lanes closer than d into this wave's kill masks.
+// The next four words are read while the current four are compared.  Lanes
+// past `live` compare stale entries of the candidate list; the ballot drops
+// them.  The rows' kills are OR-ed into the shared kill masks with LDS
+// atomics that return nothing, so no wave waits on them.
 template <int RG>
 __device__ __forceinline__ void rows_chunk(TileLds &T, int cur, int buf, unsigned int row0,
                                            unsigned int chunk, unsigned int live, uint32_t d) {
-  const unsigned int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned int lane = threadIdx.x & 63;
   uint32_t x[RG], acc0[RG], acc1[RG];
 #pragma unroll
   for (int r = 0; r < RG; ++r) {
-    const unsigned int idx = 64u * (row0 + r) + lane;
-    x[r] = idx < live ? T.cw[cur][idx] : 0u;
+    x[r] = T.cw[cur][64u * (row0 + r) + lane];  // row0 + r < kRows
     acc0[r] = acc1[r] = 0xffffffffu;
   }
   const uint4 *sp = reinterpret_cast<const uint4 *>(&T.seg[buf][64 * chunk]);
+  uint4 c = sp[0];
+  // Everything read before the loop is complete here, so the wait inside the
+  // loop only covers the read of the current four words.
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
 #pragma unroll 2
   for (int i = 0; i < 16; ++i) {
-    const uint4 c = sp[i];
+    const uint4 cn = sp[i < 15 ? i + 1 : 15];
+    __builtin_amdgcn_sched_barrier(0);  // keep the read ahead of the compares
 #pragma unroll
     for (int r = 0; r < RG; ++r) {
       acc0[r] = umin3(acc0[r], dist(x[r], c.x), dist(x[r], c.y));
       acc1[r] = umin3(acc1[r], dist(x[r], c.z), dist(x[r], c.w));
     }
+    __builtin_amdgcn_sched_barrier(0);
+    c = cn;
   }
 #pragma unroll
   for (int r = 0; r < RG; ++r) {
     const unsigned long long k = ballot(umin(acc0[r], acc1[r]) < d && 64u * (row0 + r) + lane < live);
-    if (lane == 0) T.killw[wave][row0 + r] |= k;  // this wave's own slots
+    if (lane == 0 && k) __hip_atomic_fetch_or(&T.killw[row0 + r], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 }
 
@@ -527,11 +544,13 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
 #pragma unroll
     for (int q = 0; q < kSegLoads; ++q) {
       const unsigned long long idx = lo_s + tid + (unsigned long long)q * kBlock;
-      nxt[q] = (unsigned int)(tid + q * kBlock) < l ? code[idx < hi ? idx : hi - 1] : 0u;
+      nxt[q] = (unsigned int)(tid + q * kBlock) < l ? gload(code + (idx < hi ? idx : hi - 1)) : 0u;
     }
   };
   if (off < len) fetch(off, slen);
   while (live > 0 && off < len) {
+    // The kill masks were last read before the previous compaction's barriers.
+    if (tid < kRows) T.killw[tid] = 0;
 #pragma unroll
     for (int q = 0; q < kSegLoads; ++q)  // a clipped segment repeats its oldest word
       if ((unsigned int)(tid + q * kBlock) < slen) T.seg[buf][tid + q * kBlock] = nxt[q];
@@ -551,7 +570,6 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
     // same share of the segment.
     const unsigned int rows = (live + 63) / 64, chunks = slen / 64;
     const unsigned int groups = rows > 8 ? 4u : (rows > 4 ? 2u : 1u);
-    if (lane < kRows) T.killw[wave][lane] = 0;
     for (unsigned int blk = wave; blk < groups * chunks; blk += kWaves) {
       const unsigned int g = blk / chunks, chunk = blk % chunks;
       const unsigned int row0 = g * rows / groups, rg = (g + 1) * rows / groups - row0;
@@ -565,10 +583,7 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
     __syncthreads();
     bool killed = false;
     if (tid < (int)live) {
-      unsigned long long k = 0;
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) k |= T.killw[w][tid >> 6];
-      killed = (k >> (tid & 63)) & 1;
+      killed = (T.killw[tid >> 6] >> (tid & 63)) & 1;
       word = T.cw[cur][tid];
       id = T.ci[cur][tid];
       if (killed) atomicOr(&T.dloc[(id - id0) >> 5], 1u << (id & 31));
