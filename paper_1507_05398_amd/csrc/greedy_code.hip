@@ -527,18 +527,10 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
   unsigned int live = tile_compact(T, 0, keep, word, id);
   int cur = 0, buf = 0;
   unsigned long long checks = 0;
-
-  // First claim: a short segment, so that the tile's first sweep is narrow.
-  unsigned int slen = umin(seg_len_for(live, 16), cap);
-  // Claims alternate between two LDS slots: a slot is rewritten only after the
-  // barriers of the following segment, when every thread has read it.
-  int par = 0;
-  if (tid == 0) T.claim[0] = __hip_atomic_fetch_add(cursor, (unsigned long long)slen, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-  if (tid < 32) T.dloc[tid] = 0;
-  __syncthreads();
-  unsigned long long off = T.claim[0];
   uint32_t nxt[kSegLoads];
+  auto claim = [&](unsigned int l) {
+    return __hip_atomic_fetch_add(cursor, (unsigned long long)l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
   auto fetch = [&](unsigned long long o, unsigned int l) {
     const unsigned long long hi = b - o, lo_s = hi > a + l ? hi - l : a;
 #pragma unroll
@@ -547,20 +539,34 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
       nxt[q] = (unsigned int)(tid + q * kBlock) < l ? gload(code + (idx < hi ? idx : hi - 1)) : 0u;
     }
   };
-  if (off < len) fetch(off, slen);
-  while (live > 0 && off < len) {
-    // The kill masks were last read before the previous compaction's barriers.
-    if (tid < kRows) T.killw[tid] = 0;
+  auto stage = [&](int to, unsigned int l) {
 #pragma unroll
     for (int q = 0; q < kSegLoads; ++q)  // a clipped segment repeats its oldest word
-      if ((unsigned int)(tid + q * kBlock) < slen) T.seg[buf][tid + q * kBlock] = nxt[q];
-    const unsigned int next_len = umin(seg_len_for(live, blocks), cap);
-    par ^= 1;
-    if (tid == 0) T.claim[par] = __hip_atomic_fetch_add(cursor, (unsigned long long)next_len, __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const unsigned long long next_off = T.claim[par];
-    if (next_off < len) fetch(next_off, next_len);  // in flight during the compute
+      if ((unsigned int)(tid + q * kBlock) < l) T.seg[to][tid + q * kBlock] = nxt[q];
+  };
+
+  // First claim: a short segment, so that the tile's first sweep is narrow.
+  unsigned int slen = umin(seg_len_for(live, 16), cap);
+  if (tid == 0) T.claim[0] = claim(slen);
+  if (tid < 32) T.dloc[tid] = 0;
+  if (tid < kRows) T.killw[tid] = 0;
+  __syncthreads();
+  const unsigned long long off0 = T.claim[0];
+  if (off0 >= len) return 0;
+  fetch(off0, slen);
+  unsigned int next_len = umin(seg_len_for(live, blocks), cap);
+  if (tid == 0) T.claim[1] = claim(next_len);
+  stage(buf, slen);
+  __syncthreads();
+  unsigned long long next_off = T.claim[1];
+  // Each pass: seg[buf] holds the segment being screened, and the following
+  // segment (next_off, next_len) is already claimed; it is fetched into
+  // registers during the compute and staged in the other buffer during the
+  // merge, while the claim after it is in flight.  T.claim[1] is rewritten
+  // only after the compaction's first barrier, when every thread has read it.
+  while (live > 0) {
+    const bool more = next_off < len;
+    if (more) fetch(next_off, next_len);  // in flight during the compute
     uint32_t seen = 0;
     if (tid < 32) seen = ld_relaxed(&dead[tid]);  // kills published by the other members
     // Rows go to 1, 2 or 4 groups of balanced sizes (they differ by at most
@@ -581,6 +587,11 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
     checks += 64ull * rows * slen;
     if (tid < 32) T.dseen[tid] = seen;
     __syncthreads();
+    // Claim the segment after the next one; the atomic completes during the
+    // merge and the compaction.
+    const unsigned int after_len = umin(seg_len_for(live, blocks), cap);
+    unsigned long long after_off = len;
+    if (tid == 0 && more) after_off = claim(after_len);
     bool killed = false;
     if (tid < (int)live) {
       killed = (T.killw[tid >> 6] >> (tid & 63)) & 1;
@@ -589,18 +600,23 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
       if (killed) atomicOr(&T.dloc[(id - id0) >> 5], 1u << (id & 31));
     }
     keep = tid < (int)live && !killed && !((T.dseen[(id - id0) >> 5] >> (id & 31)) & 1);
+    if (more) stage(buf ^ 1, next_len);  // that buffer was last read before the previous barrier
     // The kills are published after the compaction's first barrier, which
-    // also completes the gathering in dloc.
+    // also completes the gathering in dloc and the reads of the kill masks.
     live = tile_compact(T, cur ^ 1, keep, word, id, [&] {
       if (tid < 32) {  // one atomic per dead-bit word
         const uint32_t mine = T.dloc[tid];
         if (mine & ~T.dseen[tid]) __hip_atomic_fetch_or(&dead[tid], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
+      if (tid < kRows) T.killw[tid] = 0;
+      if (tid == 0) T.claim[1] = after_off;
     });
+    if (!more) break;
     cur ^= 1;
     buf ^= 1;
-    off = next_off;
     slen = next_len;
+    next_off = T.claim[1];
+    next_len = after_len;
   }
   return checks;
 }
