@@ -576,14 +576,23 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
     // same share of the segment.
     const unsigned int rows = (live + 63) / 64, chunks = slen / 64;
     const unsigned int groups = rows > 8 ? 4u : (rows > 4 ? 2u : 1u);
-    for (unsigned int blk = wave; blk < groups * chunks; blk += kWaves) {
+    // A wave's issue priority drops with every block it completes, so the
+    // waves of a SIMD progress together and the SIMD still has several waves
+    // to interleave when the segment's blocks run out.
+    __builtin_amdgcn_s_setprio(3);
+    unsigned int done = 0;
+    for (unsigned int blk = wave; blk < groups * chunks; blk += kWaves, ++done) {
       const unsigned int g = blk / chunks, chunk = blk % chunks;
       const unsigned int row0 = g * rows / groups, rg = (g + 1) * rows / groups - row0;
       if (rg == 4) rows_chunk<4>(T, cur, buf, row0, chunk, live, d);
       else if (rg == 3) rows_chunk<3>(T, cur, buf, row0, chunk, live, d);
       else if (rg == 2) rows_chunk<2>(T, cur, buf, row0, chunk, live, d);
       else rows_chunk<1>(T, cur, buf, row0, chunk, live, d);
+      if (done == 0) __builtin_amdgcn_s_setprio(2);
+      else if (done == 1) __builtin_amdgcn_s_setprio(1);
+      else __builtin_amdgcn_s_setprio(0);
     }
+    __builtin_amdgcn_s_setprio(0);
     checks += 64ull * rows * slen;
     if (tid < 32) T.dseen[tid] = seen;
     __syncthreads();
