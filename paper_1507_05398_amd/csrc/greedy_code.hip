@@ -527,23 +527,26 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
   unsigned int live = tile_compact(T, 0, keep, word, id);
   int cur = 0, buf = 0;
   unsigned long long checks = 0;
-  uint32_t nxt[kSegLoads];
   auto claim = [&](unsigned int l) {
     return __hip_atomic_fetch_add(cursor, (unsigned long long)l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   };
-  auto fetch = [&](unsigned long long o, unsigned int l) {
+  // The segment goes from global memory straight into LDS buffer `to` (the
+  // loads write LDS themselves; no registers hold the words).  A clipped
+  // segment repeats its oldest word.  The words are in LDS once the issuing
+  // wave's vector-memory counter drains: every wave waits for that before the
+  // barrier after which the buffer is read.
+  auto fetch = [&](unsigned long long o, unsigned int l, int to) {
     const unsigned long long hi = b - o, lo_s = hi > a + l ? hi - l : a;
 #pragma unroll
     for (int q = 0; q < kSegLoads; ++q) {
       const unsigned long long idx = lo_s + tid + (unsigned long long)q * kBlock;
-      nxt[q] = (unsigned int)(tid + q * kBlock) < l ? gload(code + (idx < hi ? idx : hi - 1)) : 0u;
+      if ((unsigned int)(tid + q * kBlock) < l)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(code + (idx < hi ? idx : hi - 1)),
+                                         (__attribute__((address_space(3))) void *)&T.seg[to][q * kBlock + 64 * wave],
+                                         4, 0, 0);
     }
   };
-  auto stage = [&](int to, unsigned int l) {
-#pragma unroll
-    for (int q = 0; q < kSegLoads; ++q)  // a clipped segment repeats its oldest word
-      if ((unsigned int)(tid + q * kBlock) < l) T.seg[to][tid + q * kBlock] = nxt[q];
-  };
+  auto fetched = [] { __builtin_amdgcn_s_waitcnt(0x0f70); };  // vmcnt(0)
 
   // First claim: a short segment, so that the tile's first sweep is narrow.
   unsigned int slen = umin(seg_len_for(live, 16), cap);
@@ -553,20 +556,21 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
   __syncthreads();
   const unsigned long long off0 = T.claim[0];
   if (off0 >= len) return 0;
-  fetch(off0, slen);
+  fetch(off0, slen, buf);
   unsigned int next_len = umin(seg_len_for(live, blocks), cap);
   if (tid == 0) T.claim[1] = claim(next_len);
-  stage(buf, slen);
+  fetched();
   __syncthreads();
   unsigned long long next_off = T.claim[1];
   // Each pass: seg[buf] holds the segment being screened, and the following
-  // segment (next_off, next_len) is already claimed; it is fetched into
-  // registers during the compute and staged in the other buffer during the
-  // merge, while the claim after it is in flight.  T.claim[1] is rewritten
-  // only after the compaction's first barrier, when every thread has read it.
+  // segment (next_off, next_len) is already claimed; it is fetched into the
+  // other buffer (last read before the previous pass's first barrier) during
+  // the compute, while the claim after it is in flight.  T.claim[1] is
+  // rewritten only after the compaction's first barrier, when every thread
+  // has read it.
   while (live > 0) {
     const bool more = next_off < len;
-    if (more) fetch(next_off, next_len);  // in flight during the compute
+    if (more) fetch(next_off, next_len, buf ^ 1);  // in flight during the compute
     uint32_t seen = 0;
     if (tid < 32) seen = ld_relaxed(&dead[tid]);  // kills published by the other members
     // Rows go to 1, 2 or 4 groups of balanced sizes (they differ by at most
@@ -609,7 +613,6 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
       if (killed) atomicOr(&T.dloc[(id - id0) >> 5], 1u << (id & 31));
     }
     keep = tid < (int)live && !killed && !((T.dseen[(id - id0) >> 5] >> (id & 31)) & 1);
-    if (more) stage(buf ^ 1, next_len);  // that buffer was last read before the previous barrier
     // The kills are published after the compaction's first barrier, which
     // also completes the gathering in dloc and the reads of the kill masks.
     live = tile_compact(T, cur ^ 1, keep, word, id, [&] {
@@ -619,6 +622,7 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
       }
       if (tid < kRows) T.killw[tid] = 0;
       if (tid == 0) T.claim[1] = after_off;
+      fetched();  // the next segment is in LDS for every wave after the barrier
     });
     if (!more) break;
     cur ^= 1;
