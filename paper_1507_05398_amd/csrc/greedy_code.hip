@@ -86,6 +86,12 @@ constexpr unsigned long long kDefaultNearGray = 8192;
 // code, where most candidates survive long ranges.
 constexpr unsigned int kNearBlocks = 16;
 constexpr unsigned int kDeepBlocks = 32;
+// Deep scans take segments of kFarBlocks blocks once the sweep is kFarAt
+// words below the newest end of its range: most survivors that a deep scan
+// kills die near that end, so deeper segments lose little to the lag of the
+// kills and halve the per-segment merges.
+constexpr unsigned int kFarBlocks = 64;
+constexpr unsigned long long kFarAt = 1ull << 19;
 constexpr unsigned int kDefaultSpin = 1u << 25;
 
 enum : int { ST_UNKNOWN = 0, ST_PASS = 1, ST_FAIL = 2 };
@@ -478,8 +484,8 @@ __device__ __forceinline__ void rows_chunk(TileLds &T, int cur, int buf, unsigne
 // Segment length (words, a multiple of 64) staged for `live` candidates: the
 // fewer live candidates, the longer the segment, so that the work per segment
 // stays near `blocks` (row group of up to 4 rows) x (64 words) blocks: 16 for
-// a tile's first segment, where most candidates die early; 64 afterwards, to
-// amortise the per-segment merge.
+// a tile's first segment, where most candidates die early; kNearBlocks,
+// kDeepBlocks or kFarBlocks afterwards, to amortise the per-segment merge.
 __device__ __forceinline__ unsigned int seg_len_for(unsigned int live, unsigned int blocks) {
   const unsigned int groups = (live + 255) / 256;
   unsigned int p2 = 1;
@@ -509,7 +515,7 @@ __device__ __forceinline__ unsigned int seg_len_for(unsigned int live, unsigned 
 __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint32_t *code, uint32_t id0,
                                           uint32_t nc, unsigned long long a, unsigned long long b,
                                           uint32_t d, unsigned long long *cursor, unsigned int members,
-                                          unsigned int blocks) {
+                                          unsigned int blocks, unsigned int far_blocks = 0) {
   TileLds &T = L.u.t;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const unsigned long long len = b > a ? b - a : 0;
@@ -557,7 +563,9 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
   const unsigned long long off0 = T.claim[0];
   if (off0 >= len) return 0;
   fetch(off0, slen, buf);
-  unsigned int next_len = umin(seg_len_for(live, blocks), cap);
+  // Segment blocks at claim offset o (words below the newest end).
+  auto blocks_at = [&](unsigned long long o) { return far_blocks && o >= kFarAt ? far_blocks : blocks; };
+  unsigned int next_len = umin(seg_len_for(live, blocks_at(off0)), cap);
   if (tid == 0) T.claim[1] = claim(next_len);
   fetched();
   __syncthreads();
@@ -602,7 +610,7 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
     __syncthreads();
     // Claim the segment after the next one; the atomic completes during the
     // merge and the compaction.
-    const unsigned int after_len = umin(seg_len_for(live, blocks), cap);
+    const unsigned int after_len = umin(seg_len_for(live, blocks_at(next_off)), cap);
     unsigned long long after_off = len;
     if (tid == 0 && more) after_off = claim(after_len);
     bool killed = false;
@@ -941,7 +949,7 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
         const uint32_t nc = (uint32_t)(L.s - id0 < (unsigned long long)kTile ? L.s - id0 : kTile);
         const unsigned long long c =
             tile_screen(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members,
-                        kDeepBlocks);
+                        kDeepBlocks, kFarBlocks);
         if (tid == 0) L.cnt_deep += c;
       });
     }
@@ -970,7 +978,7 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
           const uint32_t nc = (uint32_t)(nd - id0 < (unsigned long long)kTile ? nd - id0 : kTile);
           const unsigned long long c =
               tile_screen(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members,
-                        kDeepBlocks);
+                        kDeepBlocks, kFarBlocks);
           if (tid == 0) L.cnt_deep += c;
         });
       }
