@@ -523,19 +523,26 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
   uint32_t *dead = src.dead + (id0 >> 5);  // the tile's 32 dead-bit words
   const unsigned long long share = (len / (2ull * members) + 63) & ~63ull;
   const unsigned int cap = share < 64 ? 64u : (share > (unsigned long long)kSegMax ? (unsigned)kSegMax : (unsigned)share);
+  auto claim = [&](unsigned int l) {
+    return __hip_atomic_fetch_add(cursor, (unsigned long long)l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  // First claim: a short segment, so that the tile's first sweep is narrow.
+  // It is in flight while the candidates are listed (all of them are live:
+  // the tile's dead bits are clear when a screen starts).
+  unsigned int live = nc;
+  unsigned int slen = umin(seg_len_for(live, 16), cap);
+  unsigned long long first = 0;
+  if (tid == 0) first = claim(slen);
   bool keep = false;
   uint32_t word = 0, id = 0;
   if (tid < (int)nc) {
     id = id0 + tid;
     word = src.word(id);
-    keep = true;
+    T.cw[0][tid] = word;
+    T.ci[0][tid] = id;
   }
-  unsigned int live = tile_compact(T, 0, keep, word, id);
   int cur = 0, buf = 0;
   unsigned long long checks = 0;
-  auto claim = [&](unsigned int l) {
-    return __hip_atomic_fetch_add(cursor, (unsigned long long)l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  };
   // The segment goes from global memory straight into LDS buffer `to` (the
   // loads write LDS themselves; no registers hold the words).  A clipped
   // segment repeats its oldest word.  The words are in LDS once the issuing
@@ -554,9 +561,7 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
   };
   auto fetched = [] { __builtin_amdgcn_s_waitcnt(0x0f70); };  // vmcnt(0)
 
-  // First claim: a short segment, so that the tile's first sweep is narrow.
-  unsigned int slen = umin(seg_len_for(live, 16), cap);
-  if (tid == 0) T.claim[0] = claim(slen);
+  if (tid == 0) T.claim[0] = first;
   if (tid < 32) T.dloc[tid] = 0;
   if (tid < kRows) T.killw[tid] = 0;
   __syncthreads();
