@@ -501,8 +501,9 @@ __device__ __forceinline__ unsigned int seg_len_for(unsigned int live, unsigned 
 // b), so together they sweep the range from the newest end.  A segment is at
 // most 1/(2 members) of the range (so the last claims do not leave a few
 // members with long tails) and otherwise 64..4096 words, longer as fewer
-// candidates stay live; it is staged in LDS while the next claim is prefetched
-// into registers, and the waves split the (group of up to 4 rows of 64
+// candidates stay live (`blocks`, or `far_blocks` once the sweep is kFarAt
+// words deep); it is loaded straight into one of two LDS buffers while the
+// other is screened, and the waves split the (group of up to 4 rows of 64
 // candidates) x (chunk of 64 words) blocks.  After every segment the kills
 // are gathered into the tile's 32 dead-bit words in LDS and published with at
 // most 32 atomic ORs; the same 32 words, loaded during the compute, drop the
