@@ -15,12 +15,21 @@ Functions follow Paliwal et al., arXiv:1507.05398:
   * ``order_table``   -- the four orderings of section "Ordering
     Implementation" (readings in ``greedy_oracle.c``).
   * ``verify_certificate`` -- independent characterisation of the output.
+  * ``greedy_ball_wide`` -- ball marking for LEX/GRAY up to n = 32 (no W_ee).
+  * ``border_table`` -- section "B-ordering Implementation": the ordering an
+    ordered basis induces, by its recursive definition.
+  * ``weight_class`` -- the weight-w vectors (constant-weight candidates).
+  * ``greedy_list`` -- the plain scan over an explicit candidate list, with the
+    optional self-orthogonality constraint of section "Self Orthogonal Greedy
+    Codes Implementation".
+  * ``verify_certificate_list`` -- the certificate for a candidate list.
   * ``distance`` -- Hamming distance, section "Hamming Distance".
 
 Parity: the GREVLEX tie-break is "parity unpinned" beyond the textbook
 definition; everything else is pinned by the CPU tests.
 """
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -60,6 +69,19 @@ def _load():
     lib.gco_verify_certificate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, u32p,
                                            ctypes.c_uint64]
     lib.gco_verify_certificate.restype = ctypes.c_int
+    lib.gco_greedy_ball_wide.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, u32p,
+                                         ctypes.c_uint64, u64p, u64p]
+    lib.gco_greedy_ball_wide.restype = ctypes.c_int
+    lib.gco_border_table.argtypes = [ctypes.c_int, u32p, u32p]
+    lib.gco_border_table.restype = ctypes.c_int
+    lib.gco_weight_class.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, u32p, ctypes.c_uint64, u64p]
+    lib.gco_weight_class.restype = ctypes.c_int
+    lib.gco_greedy_list.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, u32p, ctypes.c_uint64,
+                                    u32p, ctypes.c_uint64, u64p, u64p, u64p]
+    lib.gco_greedy_list.restype = ctypes.c_int
+    lib.gco_verify_certificate_list.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, u32p,
+                                                ctypes.c_uint64, u32p, ctypes.c_uint64]
+    lib.gco_verify_certificate_list.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -130,3 +152,64 @@ def verify_certificate(n: int, d: int, ordering: int, words) -> int:
         w = np.zeros(1, dtype=np.uint32)
         return int(_load().gco_verify_certificate(n, d, ordering, _u32(w), 0))
     return int(_load().gco_verify_certificate(n, d, ordering, _u32(w), w.size))
+
+
+def greedy_ball_wide(n: int, d: int, ordering: int, cap: int = 1 << 22):
+    """Ball marking for LEX or GRAY at any n <= 32.  Returns (words, w_full)."""
+    out = np.zeros(max(cap, 1), dtype=np.uint32)
+    count, full = ctypes.c_uint64(), ctypes.c_uint64()
+    rc = _load().gco_greedy_ball_wide(n, d, ordering, _u32(out), cap, ctypes.byref(count),
+                                      ctypes.byref(full))
+    if rc:
+        raise OracleError(rc, "greedy_ball_wide")
+    return out[: count.value].copy(), full.value
+
+
+def border_table(n: int, basis) -> np.ndarray:
+    """The 2^n vectors in the order the basis b_1..b_n (basis[0] = b_1)
+    induces: 0, b_1, b_2, b_2+b_1, b_3, ... (n <= 28)."""
+    b = np.ascontiguousarray(basis, dtype=np.uint32)
+    if b.size != n:
+        raise ValueError("basis needs n words")
+    out = np.zeros(1 << n, dtype=np.uint32)
+    rc = _load().gco_border_table(n, _u32(b), _u32(out))
+    if rc:
+        raise OracleError(rc, "border_table")
+    return out
+
+
+def weight_class(n: int, w: int, ordering: int) -> np.ndarray:
+    """The weight-w vectors of F_2^n in increasing value (LEX, GRLEX) or in
+    graded reverse lexicographic order (GREVLEX)."""
+    cap = max(1, math.comb(n, w)) if 0 <= w <= n else 1
+    out = np.zeros(cap, dtype=np.uint32)
+    ln = ctypes.c_uint64()
+    rc = _load().gco_weight_class(n, w, ordering, _u32(out), cap, ctypes.byref(ln))
+    if rc:
+        raise OracleError(rc, "weight_class")
+    return out[: ln.value].copy()
+
+
+def greedy_list(n: int, d: int, candidates, self_orth: bool = False, cap: int = None):
+    """Plain-scan greedy over an explicit candidate list (optionally
+    self-orthogonal).  Returns (words, w_ee, w_full)."""
+    cand = np.ascontiguousarray(candidates, dtype=np.uint32)
+    cap = max(cand.size, 1) if cap is None else cap
+    out = np.zeros(max(cap, 1), dtype=np.uint32)
+    count, ee, full = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    rc = _load().gco_greedy_list(n, d, int(bool(self_orth)), _u32(cand) if cand.size else None,
+                                 cand.size, _u32(out), cap, ctypes.byref(count), ctypes.byref(ee),
+                                 ctypes.byref(full))
+    if rc:
+        raise OracleError(rc, "greedy_list")
+    return out[: count.value].copy(), ee.value, full.value
+
+
+def verify_certificate_list(n: int, d: int, candidates, words, self_orth: bool = False) -> int:
+    """0 if ``words`` is the greedy output over ``candidates``; else 1/2/3 =
+    order / clash / maximality rule failed (n <= 20)."""
+    cand = np.ascontiguousarray(candidates, dtype=np.uint32)
+    w = np.ascontiguousarray(words, dtype=np.uint32)
+    wp = _u32(w) if w.size else None
+    return int(_load().gco_verify_certificate_list(n, d, int(bool(self_orth)), _u32(cand), cand.size,
+                                                   wp, w.size))

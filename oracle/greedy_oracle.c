@@ -44,6 +44,27 @@
  *                       acceptance every vector of the radius-(d-1) ball is
  *                       marked.  Same output; used where the scan is too slow.
  *
+ * Extensions (the paper's other problems, same greedy rule):
+ *   gco_border_table   -- section "B-ordering Implementation": an ordered basis
+ *                         b_1..b_n induces the list 0, b_1, b_2, b_2+b_1, b_3,
+ *                         ..., built here by its recursive definition (the list
+ *                         for b_1..b_k is the list for b_1..b_{k-1} followed by
+ *                         b_k added to each of its entries).
+ *   gco_weight_class   -- section "Brief overview of the Greedy Algorithm and
+ *                         Codes": constant-weight codes take only the weight-w
+ *                         vectors as candidates, here in increasing value or
+ *                         in the graded reverse lexicographic order.
+ *   gco_greedy_list    -- the plain scan over an explicit candidate list, with
+ *                         the optional self-orthogonality constraint of section
+ *                         "Self Orthogonal Greedy Codes Implementation": a
+ *                         candidate must also have an even number of common
+ *                         ones (popcount of the AND) with itself and with every
+ *                         accepted word.
+ *   gco_verify_certificate_list -- the certificate below for a candidate list.
+ *   gco_greedy_ball_wide -- ball marking for the two positional orderings up to
+ *                         n = 32 (a 2^n-bit covered set, no per-vector index);
+ *                         it reports no W_ee.
+ *
  * Parity status: every function here is pinned by the CPU tests against the
  * paper's worked example (Example 1), closed forms (Hamming, extended Hamming
  * and Golay lexicodes, degenerate d), invariants (linearity of LEX/GRAY
@@ -358,5 +379,199 @@ int gco_verify_certificate(int n, int d, int ordering, const uint32_t *words, ui
         if (!covered) fail = 3;
     }
     free(pos); free(member); order_close(&o);
+    return fail;
+}
+
+/* ------------------------------------------------------------------ */
+/* Ball marking up to n = 32 for LEX and GRAY                          */
+/* ------------------------------------------------------------------ */
+
+/* Same rule as gco_greedy_ball (a vector is rejected exactly when it lies
+ * within d-1 of an earlier accepted word), for the positional orderings at
+ * any n <= 32, with a covered set of 2^n bits and no W_ee.  The ball around an
+ * accepted word is visited as (flips among the coordinates above the lowest
+ * L) x (flips among the lowest L), so that the inner loop stays inside one
+ * 64-byte stretch of the covered set; the set of marked vectors is the ball
+ * all the same.  w_full (may be NULL) = sum over candidates of |C| then. */
+int gco_greedy_ball_wide(int n, int d, int ordering, uint32_t *out, uint64_t cap,
+                         uint64_t *count, uint64_t *w_full)
+{
+    if (n < 1 || n > 32 || d < 1 || !count || (!out && cap)) return GCO_EINVAL;
+    if (!positional(ordering)) return GCO_EINVAL;
+    uint64_t size = 1ull << n;
+    uint8_t *covered = (uint8_t *)calloc(size / 8 + 1, 1);
+    if (!covered) return GCO_ENOMEM;
+    int r = d - 1;
+    int L = n < 9 ? n : 9;                 /* 2^9 bits = 64 bytes */
+    int H = n - L;
+    /* low flip patterns, grouped by weight */
+    uint32_t low[512];
+    int low_start[11], nlow = 0;
+    for (int k = 0; k <= L; ++k) {
+        low_start[k] = nlow;
+        for (uint32_t e = 0; e < (1u << L); ++e)
+            if (gco_weight(e) == (unsigned)k) low[nlow++] = e;
+    }
+    low_start[L + 1] = nlow;
+    uint64_t m = 0, full = 0;
+    int rc = GCO_OK;
+    for (uint64_t p = 0; p < size; ++p) {
+        uint32_t x = position_word(n, ordering, p);
+        full += m;
+        if (covered[x >> 3] & (1u << (x & 7))) continue;
+        if (m == cap) { rc = GCO_ECAPACITY; break; }
+        out[m++] = x;
+        /* every flip set = high part of size kh <= r, low part of size <= r - kh */
+        int pos[33];
+        for (int kh = 0; kh <= r && kh <= H; ++kh) {
+            for (int i = 0; i < kh; ++i) pos[i] = i;
+            for (;;) {
+                uint32_t y = x;
+                for (int i = 0; i < kh; ++i) y ^= 1u << (L + pos[i]);
+                int kl = r - kh < L ? r - kh : L;
+                for (int j = 0; j < low_start[kl + 1]; ++j) {
+                    uint32_t z = y ^ low[j];
+                    covered[z >> 3] |= (uint8_t)(1u << (z & 7));
+                }
+                int i = kh - 1;
+                while (i >= 0 && pos[i] == H - kh + i) --i;
+                if (i < 0) break;
+                ++pos[i];
+                for (int j = i + 1; j < kh; ++j) pos[j] = pos[j - 1] + 1;
+            }
+        }
+    }
+    free(covered);
+    *count = m;
+    if (rc) return rc;
+    if (w_full) *w_full = full;
+    return GCO_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* B-ordering (section "B-ordering Implementation")                    */
+/* ------------------------------------------------------------------ */
+
+/* table[0 .. 2^n) = the ordering induced by the ordered basis b_1..b_n
+ * (basis[0] = b_1), by its recursive definition: start from (0); for
+ * k = 1..n append b_k + v for every entry v of the list so far, in order.
+ * The basis is not checked for independence (a dependent one repeats
+ * vectors). */
+int gco_border_table(int n, const uint32_t *basis, uint32_t *table)
+{
+    if (n < 1 || n > GCO_TABLE_MAX_N || !basis || !table) return GCO_EINVAL;
+    uint64_t len = 1;
+    table[0] = 0;
+    for (int k = 1; k <= n; ++k) {
+        for (uint64_t i = 0; i < len; ++i) table[len + i] = basis[k - 1] ^ table[i];
+        len *= 2;
+    }
+    return GCO_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Constant weight candidates                                          */
+/* ------------------------------------------------------------------ */
+
+/* The vectors of weight w in F_2^n, in increasing value (ordering LEX or
+ * GRLEX) or in the Cox-Little-O'Shea graded reverse lexicographic order
+ * (GREVLEX), into table (room for cap entries).  *len = their number.
+ * Walks every vector of F_2^n once. */
+int gco_weight_class(int n, int w, int ordering, uint32_t *table, uint64_t cap, uint64_t *len)
+{
+    if (n < 1 || n > 32 || w < 0 || w > n || !len) return GCO_EINVAL;
+    if (ordering != GCO_LEX && ordering != GCO_GRLEX && ordering != GCO_GREVLEX) return GCO_EINVAL;
+    uint64_t size = 1ull << n, at = 0;
+    for (uint64_t x = 0; x < size; ++x) {
+        if (gco_weight((uint32_t)x) != (unsigned)w) continue;
+        if (at == cap) return GCO_ECAPACITY;
+        table[at++] = (uint32_t)x;
+    }
+    if (ordering == GCO_GREVLEX) {
+        g_sort_n = n;
+        qsort(table, at, sizeof(uint32_t), cmp_grevlex_ascending);
+    }
+    *len = at;
+    return GCO_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Plain scan over an explicit candidate list                          */
+/* ------------------------------------------------------------------ */
+
+/* Does candidate x clash with accepted word c?  Distance below d, or, with
+ * the self-orthogonality constraint, an odd number of common ones. */
+static int clash(uint32_t x, uint32_t c, int d, int self_orth)
+{
+    if (gco_distance(x, c) < (unsigned)d) return 1;
+    if (self_orth && (gco_weight(x & c) & 1u)) return 1;
+    return 0;
+}
+
+/* The greedy algorithm over cand[0 .. ncand): every candidate is compared
+ * with the accepted words newest first and appended when it clashes with
+ * none; with self_orth it must also be orthogonal to itself (even weight).
+ * Counters as in gco_greedy_scan. */
+int gco_greedy_list(int n, int d, int self_orth, const uint32_t *cand, uint64_t ncand,
+                    uint32_t *out, uint64_t cap, uint64_t *count, uint64_t *w_ee, uint64_t *w_full)
+{
+    if (n < 1 || n > 32 || d < 1 || !count || (!cand && ncand) || (!out && cap)) return GCO_EINVAL;
+    uint64_t m = 0, ee = 0, full = 0;
+    for (uint64_t p = 0; p < ncand; ++p) {
+        uint32_t x = cand[p];
+        int accept = !(self_orth && (gco_weight(x) & 1u));
+        for (uint64_t i = m; accept && i-- > 0;) {
+            ++ee;
+            if (clash(x, out[i], d, self_orth)) accept = 0;
+        }
+        full += m;
+        if (accept) {
+            if (m == cap) { *count = m; return GCO_ECAPACITY; }
+            out[m++] = x;
+        }
+    }
+    *count = m;
+    if (w_ee) *w_ee = ee;
+    if (w_full) *w_full = full;
+    return GCO_OK;
+}
+
+/* Certificate for a candidate list: words[0 .. count) is the greedy output
+ * over cand[0 .. ncand) iff (a) the words are candidates, listed in candidate
+ * order, (b) no two of them clash and, with self_orth, each has even weight,
+ * and (c) every other candidate clashes with a listed word that comes earlier
+ * in the list of candidates (or, with self_orth, has odd weight).  Brute
+ * force; candidates must be distinct and below 2^20.  Returns 0 if it holds,
+ * else 1 + the index of the failed rule. */
+int gco_verify_certificate_list(int n, int d, int self_orth, const uint32_t *cand, uint64_t ncand,
+                                const uint32_t *words, uint64_t count)
+{
+    if (n < 1 || n > 20 || d < 1 || !cand || (!words && count)) return GCO_EINVAL;
+    uint64_t size = 1ull << n;
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * size);
+    int8_t *member = (int8_t *)calloc(size, 1);
+    if (!pos || !member) { free(pos); free(member); return GCO_ENOMEM; }
+    for (uint64_t y = 0; y < size; ++y) pos[y] = -1;
+    for (uint64_t p = 0; p < ncand; ++p) pos[cand[p]] = (int64_t)p;
+    int fail = 0;
+    for (uint64_t i = 0; i < count && !fail; ++i) {
+        if (words[i] >= size || pos[words[i]] < 0) fail = 1;
+        else if (i && pos[words[i]] <= pos[words[i - 1]]) fail = 1;
+        else member[words[i]] = 1;
+    }
+    for (uint64_t i = 0; i < count && !fail; ++i) {
+        if (self_orth && (gco_weight(words[i]) & 1u)) { fail = 2; break; }
+        for (uint64_t j = i + 1; j < count; ++j)
+            if (clash(words[j], words[i], d, self_orth)) { fail = 2; break; }
+    }
+    for (uint64_t p = 0; p < ncand && !fail; ++p) {
+        uint32_t y = cand[p];
+        if (member[y]) continue;
+        int rejected = self_orth && (gco_weight(y) & 1u);
+        for (uint64_t i = 0; i < count && !rejected; ++i)
+            if (pos[words[i]] < (int64_t)p && clash(y, words[i], d, self_orth)) rejected = 1;
+        if (!rejected) fail = 3;
+    }
+    free(pos); free(member);
     return fail;
 }

@@ -11,11 +11,16 @@ exhaustive scan).  Instances (n, d, ordering):
   * lex and gray at n in {26, 28} with d=3 and at n=32 with d in {8,10,12}.
 
 Usage: python tests/golden/make_expected.py [--jobs J] [--only PREFIX]
-(about an hour on 8 cores; the n=32 instances dominate).
+(hours on 8 cores; the n=32 instances dominate).  n=32 with d=8 is built by
+ball marking (gco_greedy_ball_wide), which counts no W_ee: its W_ee is -1.
 
 With --batch it writes tests/golden/expected_batch.txt instead: the same
 fields for each of the 256 instances of the batched workload
 (paper_1507_05398_amd.workloads.batched_instances(), seed 1507), by index.
+
+With --served it writes tests/golden/expected_served.txt: |C| and SHA-256 for
+every distinct (n, d, ordering) of the served workload's 10,000-job stream
+(paper_1507_05398_amd.workloads.served_jobs(), seed 1507), by ball marking.
 """
 import argparse
 import hashlib
@@ -31,6 +36,7 @@ import oracle  # noqa: E402
 
 OUT = os.path.join(HERE, "expected_codes.txt")
 OUT_BATCH = os.path.join(HERE, "expected_batch.txt")
+OUT_SERVED = os.path.join(HERE, "expected_served.txt")
 NAMES = ["lex", "gray", "grlex", "grevlex"]
 
 
@@ -55,6 +61,12 @@ def solve(inst):
     if n <= 28 and d <= 6:
         words, w_ee, w_full = oracle.greedy_ball(n, d, ordering, want_w_ee=True, want_w_full=True)
         how = "ball"
+    elif n == 32 and d <= 8:
+        # the scan's newest-first work is out of reach here (W_full = 1.4e14);
+        # ball marking gives the code but no W_ee (recorded as -1)
+        words, w_full = oracle.greedy_ball_wide(n, d, ordering)
+        w_ee = -1
+        how = "ball-wide"
     else:
         cap = 1 << 20
         words, w_ee, w_full = oracle.greedy_scan(n, d, ordering, cap=cap)
@@ -68,9 +80,12 @@ def main():
     ap.add_argument("--jobs", type=int, default=4)
     ap.add_argument("--only", default="")
     ap.add_argument("--batch", action="store_true")
+    ap.add_argument("--served", action="store_true")
     args = ap.parse_args()
     if args.batch:
         return main_batch(args.jobs)
+    if args.served:
+        return main_served(args.jobs)
     todo = [i for i in instances() if f"{i[0]}_{i[1]}_{i[2]}".startswith(args.only)]
     old = {}
     if os.path.exists(OUT):
@@ -104,11 +119,37 @@ def main_batch(jobs):
     os.replace(OUT_BATCH + ".tmp", OUT_BATCH)
 
 
+def solve_digest(inst):
+    n, d, name = inst
+    t = time.time()
+    words, _ = oracle.greedy_ball(n, d, oracle.ORDERINGS[name])
+    digest = hashlib.sha256(words.astype("<u4").tobytes()).hexdigest()
+    return inst, len(words), digest, time.time() - t
+
+
+def main_served(jobs):
+    from paper_1507_05398_amd.workloads import served_jobs  # instance list only
+    triples = sorted({(n, d, o) for _, n, d, o in served_jobs(seed=1507, count=10000, rate=1.0)},
+                     key=lambda i: (-i[0], i[1], i[2]))
+    rows = {}
+    with ProcessPoolExecutor(jobs) as ex:
+        for (n, d, name), m, digest, dt in ex.map(solve_digest, triples):
+            rows[(n, d, name)] = f"{n}_{d}_{name} {m} {digest}"
+            print(f"served {n}_{d}_{name}: |C|={m} ({dt:.1f}s)", flush=True)
+    with open(OUT_SERVED + ".tmp", "w") as f:
+        f.write("# Written by tests/golden/make_expected.py --served from the CPU oracle only.\n")
+        f.write("# key=n_d_ordering |C| sha256(uint32 LE words in acceptance order)\n")
+        for k in sorted(rows):
+            f.write(rows[k] + "\n")
+    os.replace(OUT_SERVED + ".tmp", OUT_SERVED)
+
+
 def write(entries):
     order = [f"{i[0]}_{i[1]}_{i[2]}" for i in instances()]
     with open(OUT + ".tmp", "w") as f:
         f.write("# Written by tests/golden/make_expected.py from the CPU oracle only.\n")
         f.write("# key=n_d_ordering |C| sha256(uint32 LE words in acceptance order) W_ee W_full\n")
+        f.write("# (W_ee = -1: not counted; that code was built by ball marking)\n")
         for k in order:
             if k in entries:
                 f.write(entries[k] + "\n")

@@ -352,3 +352,236 @@ def test_plain_scan_equals_ball_marking(n, d, ordering):
     words2, w_ee2, w_full2 = oracle.greedy_ball(n, d, ordering, want_w_ee=True, want_w_full=True)
     assert np.array_equal(words, words2)
     assert (w_ee, w_full) == (w_ee2, w_full2)
+
+
+# --------------------------------------------------------------------------
+# Wide ball marking (LEX/GRAY up to n = 32): same output as the plain scan
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ordering", [oracle.LEX, oracle.GRAY])
+@pytest.mark.parametrize("n,d", [(1, 1), (4, 2), (9, 3), (10, 4), (12, 5), (13, 8), (15, 3), (16, 6)])
+def test_wide_ball_marking_equals_plain_scan(n, d, ordering):
+    words, _, w_full = oracle.greedy_scan(n, d, ordering)
+    wide, full2 = oracle.greedy_ball_wide(n, d, ordering)
+    assert np.array_equal(words, wide)
+    assert full2 == w_full
+
+
+def test_wide_ball_marking_extended_golay_lex():
+    # the n=24 d=8 lexicode is the extended Golay code (section "Some Examples")
+    words, _ = oracle.greedy_ball_wide(24, 8, oracle.LEX)
+    assert weight_distribution(words) == {0: 1, 8: 759, 12: 2576, 16: 759, 24: 1}
+
+
+# --------------------------------------------------------------------------
+# B-ordering (section "B-ordering Implementation")
+# --------------------------------------------------------------------------
+
+def gf2_rank(vectors):
+    rows, rank = [int(v) for v in vectors], 0
+    for bit in range(32):
+        piv = next((i for i in range(rank, len(rows)) if (rows[i] >> bit) & 1), None)
+        if piv is None:
+            continue
+        rows[rank], rows[piv] = rows[piv], rows[rank]
+        for i in range(len(rows)):
+            if i != rank and (rows[i] >> bit) & 1:
+                rows[i] ^= rows[rank]
+        rank += 1
+    return rank
+
+
+def random_basis(n, seed):
+    rng = np.random.default_rng(seed)
+    while True:
+        b = rng.integers(1, 1 << n, size=n, dtype=np.uint64).astype(np.uint32)
+        if gf2_rank(b) == n:
+            return b
+
+
+def test_border_listing_of_the_paper():
+    # 0, b1, b2, b2+b1, b3, b3+b1, b3+b2, b3+b2+b1 for n = 3
+    b = [0b011, 0b110, 0b100]
+    t = oracle.border_table(3, b)
+    b1, b2, b3 = b
+    assert t.tolist() == [0, b1, b2, b2 ^ b1, b3, b3 ^ b1, b3 ^ b2, b3 ^ b2 ^ b1]
+
+
+@pytest.mark.parametrize("n", [1, 3, 8, 14])
+def test_border_unit_basis_is_lex_and_gray_basis_is_gray(n):
+    unit = [1 << j for j in range(n)]
+    assert np.array_equal(oracle.border_table(n, unit), oracle.order_table(n, oracle.LEX))
+    # b_1 = 1, b_j = 2^(j-1) + 2^(j-2): the reflected Gray code (built by reflection)
+    gray = [1] + [(1 << j) | (1 << (j - 1)) for j in range(1, n)]
+    assert np.array_equal(oracle.border_table(n, gray), oracle.order_table(n, oracle.GRAY))
+
+
+@pytest.mark.parametrize("n", [5, 11, 16])
+def test_border_independent_basis_is_a_bijection(n):
+    t = oracle.border_table(n, random_basis(n, n))
+    assert t[0] == 0
+    assert np.array_equal(np.sort(t), np.arange(1 << n, dtype=np.uint32))
+
+
+@pytest.mark.parametrize("n,d", [(10, 3), (13, 4), (15, 3), (16, 5)])
+def test_border_with_permuted_unit_basis_is_permuted_lexicode(n, d):
+    # b_j = 2^sigma(j): position p lists sigma applied to the bits of p, and a
+    # permutation of coordinates keeps distances, so the code is sigma(lexicode)
+    sigma = np.random.default_rng(n * 31 + d).permutation(n)
+    basis = [1 << int(sigma[j]) for j in range(n)]
+    words, _, _ = oracle.greedy_list(n, d, oracle.border_table(n, basis))
+    lexi, _, _ = oracle.greedy_scan(n, d, oracle.LEX)
+
+    def permute(x):
+        return sum(1 << int(sigma[j]) for j in range(n) if (int(x) >> j) & 1)
+
+    assert [int(w) for w in words] == [permute(x) for x in lexi]
+
+
+@pytest.mark.parametrize("n,d", [(9, 3), (11, 4), (12, 5), (14, 3), (14, 6)])
+def test_border_greedy_codes_are_linear(n, d):
+    # B-greedy codes are linear (Brualdi and Pless, cited in the B-ordering
+    # section): |C| = 2^k and the code is closed under XOR
+    for seed in range(3):
+        words, _, _ = oracle.greedy_list(n, d, oracle.border_table(n, random_basis(n, 100 * n + seed)))
+        k = int(math.log2(len(words)))
+        assert len(words) == 1 << k
+        s = set(int(w) for w in words)
+        assert all((int(a) ^ int(b)) in s for a in words[:40] for b in words)
+
+
+@pytest.mark.parametrize("n,d", [(8, 3), (10, 4), (12, 3)])
+def test_border_greedy_satisfies_certificate(n, d):
+    table = oracle.border_table(n, random_basis(n, 7 * n + d))
+    words, _, _ = oracle.greedy_list(n, d, table)
+    assert oracle.verify_certificate_list(n, d, table, words) == 0
+    bad = words.copy()
+    bad[-1] ^= 1
+    assert oracle.verify_certificate_list(n, d, table, bad) != 0
+
+
+# --------------------------------------------------------------------------
+# Constant-weight codes (section "Brief overview ...": given n, d and w)
+# --------------------------------------------------------------------------
+
+def test_weight_class_listings_by_hand():
+    assert [format(int(x), "04b") for x in oracle.weight_class(4, 2, oracle.LEX)] == \
+        ["0011", "0101", "0110", "1001", "1010", "1100"]
+    assert [format(int(x), "04b") for x in oracle.weight_class(4, 2, oracle.GREVLEX)] == \
+        ["0011", "0101", "1001", "0110", "1010", "1100"]
+    assert oracle.weight_class(5, 0, oracle.LEX).tolist() == [0]
+    assert oracle.weight_class(5, 5, oracle.GRLEX).tolist() == [31]
+
+
+@pytest.mark.parametrize("n,w", [(6, 3), (10, 4), (12, 1), (13, 6)])
+def test_weight_class_sizes_and_weights(n, w):
+    c = oracle.weight_class(n, w, oracle.LEX)
+    assert len(c) == math.comb(n, w)
+    assert all(bin(int(x)).count("1") == w for x in c)
+    assert np.all(np.diff(c.astype(np.int64)) > 0)
+
+
+@pytest.mark.parametrize("n,w", [(8, 3), (11, 4), (12, 5), (9, 2)])
+def test_constant_weight_closed_forms(n, w):
+    c = oracle.weight_class(n, w, oracle.LEX)
+    # distinct words of one weight differ in at least 2 places: d <= 2 keeps all
+    assert len(oracle.greedy_list(n, 2, c)[0]) == len(c)
+    # distance 2w means disjoint supports: the greedy takes consecutive blocks
+    words = oracle.greedy_list(n, 2 * w, c)[0]
+    assert [int(x) for x in words] == [((1 << w) - 1) << (w * i) for i in range(n // w)]
+    # odd d behaves as d + 1 (distances between equal-weight words are even)
+    assert np.array_equal(oracle.greedy_list(n, 2 * w - 1, c)[0], words)
+    # above 2w only the first word fits
+    assert oracle.greedy_list(n, 2 * w + 1, c)[0].tolist() == [(1 << w) - 1]
+
+
+@pytest.mark.parametrize("n", [7, 15, 31])
+def test_constant_weight_triples_are_projective_steiner_systems(n):
+    # n = 2^m - 1, w = 3, d = 4: the lexicographic code is the Steiner triple
+    # system of points and lines of PG(m-1, 2), n(n-1)/6 triples, every pair
+    # of points in exactly one triple
+    words = oracle.greedy_list(n, 4, oracle.weight_class(n, 3, oracle.LEX))[0]
+    assert len(words) == n * (n - 1) // 6
+    pairs = set()
+    for x in words:
+        pts = [j for j in range(n) if (int(x) >> j) & 1]
+        for a, b in itertools.combinations(pts, 2):
+            assert (a, b) not in pairs
+            pairs.add((a, b))
+    assert len(pairs) == n * (n - 1) // 2
+
+
+def johnson_bound(n, d, w):
+    # A(n, 2t, w) <= floor(n/w * A(n-1, 2t, w-1)), with A = 1 once w < t
+    t = (d + 1) // 2
+    if w < t:
+        return 1
+    return n * johnson_bound(n - 1, d, w - 1) // w
+
+
+@pytest.mark.parametrize("ordering", [oracle.LEX, oracle.GREVLEX])
+@pytest.mark.parametrize("n,d,w", [(10, 4, 4), (12, 6, 5), (13, 4, 3), (14, 6, 4), (11, 8, 5)])
+def test_constant_weight_bounds_and_certificate(n, d, w, ordering):
+    c = oracle.weight_class(n, w, ordering)
+    words = oracle.greedy_list(n, d, c)[0]
+    assert len(words) <= johnson_bound(n, d, w)
+    assert oracle.verify_certificate_list(n, d, c, words) == 0
+
+
+# --------------------------------------------------------------------------
+# Self-orthogonal greedy codes (section "Self Orthogonal Greedy Codes
+# Implementation"; section "Some Examples")
+# --------------------------------------------------------------------------
+
+def macwilliams_self_dual(dist, n):
+    # weight enumerator of the dual: B_j = 2^-k sum_i A_i K_j(i), with the
+    # Krawtchouk polynomial K_j(i) = sum_s (-1)^s C(i, s) C(n - i, j - s)
+    size = sum(dist.values())
+    out = {}
+    for j in range(n + 1):
+        tot = 0
+        for i, a in dist.items():
+            tot += a * sum((-1) ** s * math.comb(i, s) * math.comb(n - i, j - s) for s in range(j + 1))
+        assert tot % size == 0
+        if tot:
+            out[j] = tot // size
+    return out
+
+
+@pytest.mark.parametrize("n,d,dist", [
+    (8, 4, {0: 1, 4: 14, 8: 1}),                          # extended Hamming [8,4,4]
+    (22, 6, {0: 1, 6: 77, 8: 330, 10: 616, 12: 616, 14: 330, 16: 77, 22: 1}),  # self-dual [22,11,6]
+    (24, 8, {0: 1, 8: 759, 12: 2576, 16: 759, 24: 1}),   # extended Golay [24,12,8]
+])
+def test_self_orthogonal_lexicodes_are_the_classical_self_dual_codes(n, d, dist):
+    # the paper: self-orthogonal greedy generation gives the extended Golay
+    # code [24,12,8]; Monroe's codes include the [22,11,6] one
+    words = oracle.greedy_list(n, d, oracle.order_table(n, oracle.LEX), self_orth=True)[0]
+    assert weight_distribution(words) == dist
+    # self-dual: |C| = 2^(n/2) and the enumerator is its own MacWilliams transform
+    assert len(words) == 1 << (n // 2)
+    assert macwilliams_self_dual(dist, n) == dist
+
+
+@pytest.mark.parametrize("ordering", ORDS)
+@pytest.mark.parametrize("n,d", [(10, 2), (12, 4), (13, 3), (14, 6)])
+def test_self_orthogonal_outputs_are_orthogonal_and_certified(n, d, ordering):
+    table = oracle.order_table(n, ordering)
+    words = oracle.greedy_list(n, d, table, self_orth=True)[0]
+    assert all(bin(int(x)).count("1") % 2 == 0 for x in words)
+    for a in words:
+        for b in words:
+            assert bin(int(a) & int(b)).count("1") % 2 == 0
+    assert len(words) <= 1 << (n // 2)
+    assert oracle.verify_certificate_list(n, d, table, words, self_orth=True) == 0
+    bad = words.copy()
+    bad[-1] ^= 3
+    assert oracle.verify_certificate_list(n, d, table, bad, self_orth=True) != 0
+
+
+@pytest.mark.parametrize("ordering", ORDS)
+@pytest.mark.parametrize("n,d", [(9, 3), (12, 4), (14, 5)])
+def test_list_scan_without_constraint_is_the_plain_scan(n, d, ordering):
+    a, ee, full = oracle.greedy_scan(n, d, ordering)
+    b, ee2, full2 = oracle.greedy_list(n, d, oracle.order_table(n, ordering))
+    assert np.array_equal(a, b) and ee == ee2 and full == full2
