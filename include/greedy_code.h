@@ -106,8 +106,10 @@ int greedy_code(int n, int d, int ordering, uint32_t *out_words, uint64_t *out_c
 /* Device-memory entry point: the words go to d_words (device array of
  * `capacity` uint32, caller-owned, e.g. a torch tensor's data_ptr), the count
  * to *d_count (one device uint64), both written on `hip_stream` (a
- * hipStream_t, NULL = null stream).  The library allocates a temporary device
- * workspace (about 2.5 MiB) stream-ordered and releases it before returning.
+ * hipStream_t, NULL = null stream).  The call uses a device workspace of
+ * about 1 MiB from a pool the library keeps per device (allocated with
+ * hipMalloc the first time a call needs one, reused by later calls, held
+ * until the process ends; concurrent calls get distinct workspaces).
  * GC_ECAPACITY: the first `capacity` words and *d_count = capacity. */
 int greedy_code_device(int n, int d, int ordering, uint32_t *d_words, uint64_t capacity,
                        uint64_t *d_count, void *hip_stream);
@@ -171,8 +173,8 @@ int gc_batch_graph_destroy(gc_batch_graph *graph);
  * time in *best_ms, may be NULL).  The choice is remembered per device and
  * (n, d, ordering): later builds of that instance that pass no tuning
  * (greedy_code, greedy_code_device, greedy_code_device_ex with tuning NULL,
- * batch jobs, server jobs) use it.  Allocates a scratch code buffer on the
- * stream for the duration of the call.  d <= 1 or d > n: nothing to tune,
+ * batch jobs, server jobs) use it.  Allocates a scratch code buffer
+ * (hipMalloc) for the duration of the call.  d <= 1 or d > n: nothing to tune,
  * *best is zeroed.  GC_EDEVICE if two candidates disagree. */
 int greedy_code_tune(int n, int d, int ordering, void *hip_stream, gc_tuning *best, float *best_ms);
 
@@ -191,16 +193,24 @@ int greedy_code_batch_tune(gc_job *jobs, int njobs, void *hip_stream, int *best_
  * for its worst-case code (greedy_code_capacity(n, d) words); admitted jobs
  * go to a queue in pinned host memory that the running kernel's teams pull
  * from, so a job arriving while others build starts as soon as a team frees
- * up.  Finished codes stay resident in the arena until released.  The
- * kernel exits after about 0.1 s without work and is relaunched on demand.
- * Not thread-safe across servers' destroy; every call on one server is
- * serialised by an internal lock. */
+ * up.  Jobs run in arrival order.  With more than one team, a job whose
+ * exhaustive work bound 2^n * greedy_code_capacity(n, d) is at least 2^38
+ * ("wide") is built by a launch whose single team spans the GPU, and the
+ * other jobs by the narrow teams: a launch stops claiming at the first job
+ * of the other kind and the server relaunches with the shape that job needs.
+ * Finished codes stay resident in the arena until released.  The kernel
+ * exits after about 0.1 s without work and is relaunched on demand.  If a
+ * bounded device-side wait expires, every unfinished job fails with
+ * GC_ETIMEOUT (gc_server_poll reports GC_JOB_FAILED) and the server accepts
+ * no further jobs.  Not thread-safe across servers' destroy; every call on
+ * one server is serialised by an internal lock. */
 typedef struct gc_server gc_server;
 
 /* arena_bytes: device memory for resident codes (the server also allocates
  * as much pinned host memory: each finished code is written there by the
  * kernel itself, so fetching a result needs no device copy while the kernel
- * holds the GPU); teams: 1, 2, 4 or 8. */
+ * holds the GPU); teams: narrow teams, 1, 2, 4 or 8 (1: every job on one
+ * team spanning the GPU). */
 int gc_server_create(size_t arena_bytes, int teams, gc_server **out);
 /* Queue a job; *ticket identifies it.  GC_ENOMEM if its worst-case code can
  * never fit the arena. */
@@ -219,7 +229,8 @@ int gc_server_stats(gc_server *srv, uint64_t ticket, gc_stats *stats, double *de
 int gc_server_release(gc_server *srv, uint64_t ticket);
 /* Wait until no job is waiting or building; timeout_ms < 0 waits forever. */
 int gc_server_drain(gc_server *srv, int timeout_ms);
-/* Stop the kernel and free everything (outstanding jobs are abandoned). */
+/* Stop the kernel and free everything (jobs not yet claimed by the device are
+ * abandoned; the kernel finishes the ones it is building first). */
 int gc_server_destroy(gc_server *srv);
 
 /* Message of the last failed call on this thread ("" if none). */

@@ -37,6 +37,7 @@ struct Job {
   unsigned long long t_claim, t_done;  // device wall clock (100 MHz) at claim / completion
   int status;
   unsigned int done;              // 0 pending, 1 finished (written last)
+  int wide;                       // server: built only by a launch whose one team spans the GPU
 };
 
 // Job queue.  `submitted` and `shutdown` may live in host memory (server);
@@ -86,6 +87,8 @@ struct Params {
   Bar *bar;
   int njobs_fixed;               // batch: number of jobs; server: -1 (read hq->submitted)
   int nteams;
+  int claim_kind;                // server: 0 claims every job, 1 only narrow jobs, 2 only wide
+                                 // jobs (a team stops at the first job of the other kind)
   unsigned int spin_limit;       // bounded waits inside a job
   unsigned int idle_limit;       // server: polls of an empty queue before the kernel exits
   char *team_ws;                 // per-team workspace, team_ws_stride bytes each

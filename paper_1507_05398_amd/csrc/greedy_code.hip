@@ -1025,15 +1025,19 @@ __device__ int claim_job(const Params &P) {
   unsigned int idle = 0;
   for (;;) {
     if (ld_relaxed(&P.dq->abort)) return -1;
-    const unsigned int sub = ld_sys(&P.hq->submitted);
+    if (ld_sys(&P.hq->shutdown)) return -1;  // outstanding jobs are abandoned
+    // Acquire: the job descriptors the host published before `submitted`.
+    const unsigned int sub = __hip_atomic_load(&P.hq->submitted, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
     unsigned int c = ld_relaxed(&P.dq->claimed);
     if (c < sub) {
+      // A launch of one kind stops at the first job of the other kind; the
+      // host then relaunches with the team shape that job needs.
+      if (P.claim_kind != 0 && (ld_sys(&P.jobs[c].wide) != 0) != (P.claim_kind == 2)) return -1;
       if (__hip_atomic_compare_exchange_strong(&P.dq->claimed, &c, c + 1, __ATOMIC_RELAXED,
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
         return (int)c;
       continue;
     }
-    if (ld_sys(&P.hq->shutdown)) return -1;
     if (++idle > P.idle_limit) return -1;
     __builtin_amdgcn_s_sleep(8);
   }
@@ -1299,6 +1303,78 @@ unsigned int spin_limit_from_env() {
   return s;
 }
 
+// Device workspaces of the plain entry points.  A call takes a free one of
+// sufficient size (allocated with hipMalloc the first time it is needed) and
+// gives it back when its stream has finished with it; the library keeps them
+// for reuse until the process ends and never frees them from an exit handler.
+// Concurrent calls on one device get distinct workspaces.
+struct WsEntry {
+  int dev;
+  char *ptr;
+  size_t bytes;
+  bool busy;
+};
+std::mutex g_ws_mu;
+std::vector<WsEntry> g_ws;
+
+int acquire_workspace(size_t bytes, char **ptr, int *slot) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  for (size_t i = 0; i < g_ws.size(); ++i) {
+    WsEntry &e = g_ws[i];
+    if (!e.busy && e.dev == dev && e.bytes >= bytes) {
+      e.busy = true;
+      *ptr = e.ptr;
+      *slot = (int)i;
+      return GC_OK;
+    }
+  }
+  const size_t rounded = (bytes + (1u << 20) - 1) & ~(size_t)((1u << 20) - 1);
+  char *p = nullptr;
+  const hipError_t e = hipMalloc((void **)&p, rounded);
+  if (e != hipSuccess) return fail(GC_ENOMEM, "workspace of %zu bytes: %s", rounded, hipGetErrorString(e));
+  g_ws.push_back(WsEntry{dev, p, rounded, true});
+  *ptr = p;
+  *slot = (int)g_ws.size() - 1;
+  return GC_OK;
+}
+
+void release_workspace(int slot) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  if (slot >= 0 && (size_t)slot < g_ws.size()) g_ws[slot].busy = false;
+}
+
+// Byte layout of a launch workspace: barrier block, device queue, job table,
+// then one workspace per team.
+struct LaunchLayout {
+  size_t off_dq, off_jobs, off_ws, bytes;
+};
+LaunchLayout launch_layout(int njobs, int nteams) {
+  LaunchLayout l;
+  l.off_dq = align256(sizeof(Bar));
+  l.off_jobs = l.off_dq + align256(sizeof(DevQueue));
+  l.off_ws = l.off_jobs + align256(sizeof(Job) * (size_t)njobs);
+  l.bytes = l.off_ws + kTeamWsBytes * (size_t)nteams;
+  return l;
+}
+
+Params launch_params(char *ws, const LaunchLayout &l, int njobs, int nteams) {
+  Params P;
+  memset(&P, 0, sizeof(P));
+  P.jobs = reinterpret_cast<Job *>(ws + l.off_jobs);
+  P.hq = nullptr;
+  P.dq = reinterpret_cast<DevQueue *>(ws + l.off_dq);
+  P.bar = reinterpret_cast<Bar *>(ws);
+  P.njobs_fixed = njobs;
+  P.nteams = nteams;
+  P.spin_limit = spin_limit_from_env();
+  P.idle_limit = 0;
+  P.team_ws = ws + l.off_ws;
+  P.team_ws_stride = kTeamWsBytes;
+  return P;
+}
+
 // Run a batch of jobs on `stream` with `nteams` teams and wait for it.  Jobs
 // are copied to device memory and their outputs copied back into `jobs`.
 int run_batch(Job *jobs, int njobs, int nteams, unsigned int grid_req, hipStream_t stream,
@@ -1309,26 +1385,12 @@ int run_batch(Job *jobs, int njobs, int nteams, unsigned int grid_req, hipStream
   unsigned int grid = 0;
   int rc = pick_grid(grid_req, &grid);
   if (rc) return rc;
-  const size_t off_bar = 0;
-  const size_t off_dq = align256(sizeof(Bar));
-  const size_t off_jobs = off_dq + align256(sizeof(DevQueue));
-  const size_t off_ws = off_jobs + align256(sizeof(Job) * (size_t)njobs);
-  const size_t bytes = off_ws + kTeamWsBytes * (size_t)nteams;
+  const LaunchLayout lay = launch_layout(njobs, nteams);
   char *ws = nullptr;
-  HIP_TRY(hipMallocAsync((void **)&ws, bytes, stream));
-  Params P;
-  memset(&P, 0, sizeof(P));
-  P.jobs = reinterpret_cast<Job *>(ws + off_jobs);
-  P.hq = nullptr;
-  P.dq = reinterpret_cast<DevQueue *>(ws + off_dq);
-  P.bar = reinterpret_cast<Bar *>(ws + off_bar);
-  P.njobs_fixed = njobs;
-  P.nteams = nteams;
-  P.spin_limit = spin_limit_from_env();
-  P.idle_limit = 0;
-  P.team_ws = ws + off_ws;
-  P.team_ws_stride = kTeamWsBytes;
-
+  int slot = -1;
+  rc = acquire_workspace(lay.bytes, &ws, &slot);
+  if (rc) return rc;
+  const Params P = launch_params(ws, lay, njobs, nteams);
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipError_t e = hipEventCreate(&ev0);
   if (e == hipSuccess) e = hipEventCreate(&ev1);
@@ -1341,13 +1403,14 @@ int run_batch(Job *jobs, int njobs, int nteams, unsigned int grid_req, hipStream
   memset(&dq, 0, sizeof(dq));
   if (e == hipSuccess) e = hipMemcpyAsync(jobs, P.jobs, sizeof(Job) * njobs, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipMemcpyAsync(&dq, P.dq, sizeof(dq), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  // The workspace goes back to the pool only once the stream is idle.
+  const hipError_t es = hipStreamSynchronize(stream);
+  if (e == hipSuccess) e = es;
   if (e == hipSuccess && kernel_ms) e = hipEventElapsedTime(kernel_ms, ev0, ev1);
-  const hipError_t ef = hipFreeAsync(ws, stream);
+  if (es == hipSuccess) release_workspace(slot);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
   if (e != hipSuccess) return fail(GC_EDEVICE, "persistent kernel failed: %s", hipGetErrorString(e));
-  if (ef != hipSuccess) return fail(GC_EDEVICE, "hipFreeAsync failed: %s", hipGetErrorString(ef));
   if (dq.abort) return fail(GC_ETIMEOUT, "a bounded device-side wait expired");
   return GC_OK;
 }
@@ -1571,7 +1634,7 @@ int greedy_code_tune(int n, int d, int ordering, void *hip_stream, gc_tuning *be
       {16384ull, 0, 0, 2, 0},     {16384ull, 0, 0, 1, 0}, {4096ull, 0, 0, 2, 0},
   };
   uint32_t *words = nullptr;
-  HIP_TRY(hipMallocAsync((void **)&words, (size_t)cap * sizeof(uint32_t), st));
+  HIP_TRY(hipMalloc((void **)&words, (size_t)cap * sizeof(uint32_t)));
   std::vector<uint32_t> ref, cur;
   uint64_t ref_m = 0;
   float best_t = 0.f;
@@ -1612,9 +1675,10 @@ int greedy_code_tune(int n, int d, int ordering, void *hip_stream, gc_tuning *be
       *best = t;
     }
   }
-  const hipError_t ef = hipFreeAsync(words, st);
+  (void)hipStreamSynchronize(st);
+  const hipError_t ef = hipFree(words);
   if (rc) return rc;
-  if (ef != hipSuccess) return fail(GC_EDEVICE, "hipFreeAsync failed: %s", hipGetErrorString(ef));
+  if (ef != hipSuccess) return fail(GC_EDEVICE, "hipFree failed: %s", hipGetErrorString(ef));
   if (best_ms) *best_ms = best_t;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tuned[TuneKey{dev, n, d, ordering}] = *best;

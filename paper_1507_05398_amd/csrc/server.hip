@@ -17,6 +17,7 @@
 
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <deque>
 #include <iterator>
 #include <thread>
@@ -32,11 +33,18 @@ namespace gcimpl {
 
 constexpr unsigned int kServerSlots = 1u << 16;   // jobs over the life of one server
 constexpr unsigned int kServerIdlePolls = 50000;  // about 0.1 s of empty queue before the kernel exits
+// A job whose exhaustive work bound 2^n * capacity(n, d) reaches this is
+// "wide": it is built by a launch whose single team spans the GPU (on one
+// XCD's team it would take up to eight times longer and stretch the
+// makespan); the other jobs share the narrow teams.
+constexpr double kWideWork = 274877906944.0;  // 2^38
 
 struct Ticket {
   int n, d, ord;
   size_t bytes = 0, offset = 0;
+  bool has_space = false;   // owns `bytes` of the arena at `offset`
   int state = GC_JOB_WAITING;
+  int status = 0;           // GC_OK, or the failure code once FAILED
   int slot = -1;
 };
 
@@ -44,7 +52,8 @@ struct Ticket {
 
 struct gc_server {
   std::mutex mu;
-  int teams = 8;
+  int teams = 8;            // narrow teams (jobs below the wide threshold)
+  bool stopped = false;     // a bounded device-side wait expired: no further launches
   unsigned int grid = 0;
   hipStream_t stream = nullptr;
   hipEvent_t kernel_done = nullptr;
@@ -113,7 +122,14 @@ bool kernel_running(gc_server *s) {
   return hipEventQuery(s->kernel_done) == hipErrorNotReady;
 }
 
-int launch_server_kernel(gc_server *s) {
+bool is_wide(const gc_server *s, int n, int d) {
+  return s->teams > 1 && std::ldexp((double)greedy_code_capacity(n, d), n) >= kWideWork;
+}
+
+// Launch the persistent kernel for the next unclaimed job: one GPU-wide team
+// if that job is wide, the narrow teams otherwise.  Each launch stops at the
+// first job of the other kind.
+int launch_server_kernel(gc_server *s, bool wide) {
   Params P;
   memset(&P, 0, sizeof(P));
   P.jobs = s->jobs_dev;
@@ -121,7 +137,8 @@ int launch_server_kernel(gc_server *s) {
   P.dq = s->dq;
   P.bar = s->bar;
   P.njobs_fixed = -1;
-  P.nteams = s->teams;
+  P.nteams = wide ? 1 : s->teams;
+  P.claim_kind = s->teams == 1 ? 0 : (wide ? 2 : 1);
   P.spin_limit = 1u << 25;
   if (const char *env = getenv("GC_SPIN_LIMIT")) P.spin_limit = (unsigned int)strtoul(env, nullptr, 0);
   P.idle_limit = kServerIdlePolls;
@@ -135,9 +152,35 @@ int launch_server_kernel(gc_server *s) {
   return GC_OK;
 }
 
+// Every job not yet finished fails with `code` (waiting ones included), and
+// the server launches nothing more.  Jobs the device did finish keep their
+// results.
+void fail_unfinished(gc_server *s, int code) {
+  s->stopped = true;
+  for (uint64_t id : s->inflight) {
+    Ticket &t = s->tickets[id];
+    const Job &J = s->jobs[t.slot];
+    if (__atomic_load_n(&J.done, __ATOMIC_ACQUIRE)) {
+      t.status = J.status;
+      t.state = t.status == 0 ? GC_JOB_DONE : GC_JOB_FAILED;
+    } else {
+      t.state = GC_JOB_FAILED;
+      t.status = code;
+    }
+  }
+  s->inflight.clear();
+  for (uint64_t id : s->waiting) {
+    Ticket &t = s->tickets[id];
+    t.state = GC_JOB_FAILED;
+    t.status = code;
+  }
+  s->waiting.clear();
+}
+
 // Admit waiting jobs in arrival order while the arena has room, publish them,
 // and make sure a kernel is running while published work is unfinished.
 int pump(gc_server *s) {
+  if (s->stopped) return GC_OK;
   bool published_any = false;
   while (!s->waiting.empty()) {
     const uint64_t id = s->waiting.front();
@@ -150,6 +193,7 @@ int pump(gc_server *s) {
     }
     s->waiting.pop_front();
     t.offset = off;
+    t.has_space = true;
     t.slot = (int)s->published;
     t.state = GC_JOB_ADMITTED;
     Job *J = &s->jobs[t.slot];
@@ -161,6 +205,7 @@ int pump(gc_server *s) {
     J->capacity = greedy_code_capacity(t.n, t.d);
     J->count = nullptr;
     J->host_copy = reinterpret_cast<uint32_t *>(s->mirror_dev + off);
+    J->wide = is_wide(s, t.n, t.d) ? 1 : 0;
     gc_tuning tu;
     if (tuned_for(t.n, t.d, t.ord, &tu)) {
       J->near_depth = tu.near_depth;
@@ -177,7 +222,8 @@ int pump(gc_server *s) {
     __atomic_store_n(&s->hq->submitted, s->published, __ATOMIC_RELEASE);
   }
   // Relaunch if published jobs are unfinished and no kernel is running (the
-  // previous one may have gone idle just before the publication).
+  // previous one may have gone idle just before the publication, stopped at
+  // a job of the other kind, or given up on a bounded wait).
   if (!kernel_running(s)) {
     bool unfinished = false;
     for (uint64_t id : s->inflight)
@@ -185,14 +231,33 @@ int pump(gc_server *s) {
         unfinished = true;
         break;
       }
-    if (unfinished) return launch_server_kernel(s);
+    if (!unfinished) return GC_OK;
+    // The last launch has finished: its queue state tells where to resume.
+    DevQueue dq;
+    memset(&dq, 0, sizeof(dq));
+    hipError_t e = hipSuccess;
+    if (s->launched) {
+      e = hipMemcpyAsync(&dq, s->dq, sizeof(dq), hipMemcpyDeviceToHost, s->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+      if (e != hipSuccess) return fail(GC_EDEVICE, "server queue read failed: %s", hipGetErrorString(e));
+    }
+    if (dq.abort) {
+      // A device-side wait expired: the jobs that launch claimed are lost,
+      // and the device made no guaranteed progress; stop here rather than
+      // relaunch.
+      fail_unfinished(s, GC_ETIMEOUT);
+      return GC_OK;
+    }
+    const bool wide = dq.claimed < s->published && s->jobs[dq.claimed].wide;
+    return launch_server_kernel(s, wide);
   }
   return GC_OK;
 }
 
 void refresh(gc_server *s, uint64_t id, Ticket &t) {
   if (t.state == GC_JOB_ADMITTED && __atomic_load_n(&s->jobs[t.slot].done, __ATOMIC_ACQUIRE)) {
-    t.state = s->jobs[t.slot].status == 0 ? GC_JOB_DONE : GC_JOB_FAILED;
+    t.status = s->jobs[t.slot].status;
+    t.state = t.status == 0 ? GC_JOB_DONE : GC_JOB_FAILED;
     s->inflight.erase(id);
   }
 }
@@ -258,6 +323,7 @@ int gc_server_submit(gc_server *s, int n, int d, int ordering, uint64_t *ticket)
   if (n < 1 || n > 32 || d < 1 || ordering < GC_LEX || ordering > GC_GREVLEX)
     return fail(GC_EINVAL, "invalid job n=%d d=%d ordering=%d", n, d, ordering);
   std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stopped) return fail(GC_ETIMEOUT, "server stopped after a device-side wait expired");
   Ticket t;
   t.n = n;
   t.d = d;
@@ -294,7 +360,7 @@ int gc_server_words(gc_server *s, uint64_t ticket, const uint32_t **d_words, uin
   if (it == s->tickets.end()) return fail(GC_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
   refresh(s, it->first, it->second);
   if (it->second.state == GC_JOB_FAILED)
-    return fail(s->jobs[it->second.slot].status, "job failed with status %d", s->jobs[it->second.slot].status);
+    return fail(it->second.status, "job failed with status %d", it->second.status);
   if (it->second.state != GC_JOB_DONE) return fail(GC_EBUSY, "job not finished");
   *d_words = reinterpret_cast<const uint32_t *>(s->arena + it->second.offset);
   *count = s->jobs[it->second.slot].out_count;
@@ -327,7 +393,7 @@ int gc_server_release(gc_server *s, uint64_t ticket) {
   refresh(s, it->first, it->second);
   if (it->second.state == GC_JOB_WAITING || it->second.state == GC_JOB_ADMITTED)
     return fail(GC_EBUSY, "job not finished");
-  arena_free(s, it->second.offset, it->second.bytes);
+  if (it->second.has_space) arena_free(s, it->second.offset, it->second.bytes);
   s->tickets.erase(it);
   return pump(s);
 }
@@ -341,6 +407,7 @@ int gc_server_stats(gc_server *s, uint64_t ticket, gc_stats *stats, double *devi
   refresh(s, it->first, it->second);
   if (it->second.state != GC_JOB_DONE && it->second.state != GC_JOB_FAILED)
     return fail(GC_EBUSY, "job not finished");
+  if (it->second.slot < 0) return fail(it->second.status, "job failed before it was admitted");
   const Job &J = s->jobs[it->second.slot];
   if (stats) {
     memset(stats, 0, sizeof(*stats));

@@ -206,3 +206,77 @@ def test_served_workload_sample_matches_oracle():
     assert waited > 0  # some jobs did wait for memory
     for i, (_, n, d, o) in enumerate(jobs):
         np.testing.assert_array_equal(got[i], ref(n, d, o))
+
+
+def load_served_digests():
+    path = os.path.join(HERE, "golden", "expected_served.txt")
+    out = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            key, m, digest = line.split()
+            out[key] = (int(m), digest)
+    return out
+
+
+def test_served_triples_match_oracle_digests():
+    """Every distinct (n, d, ordering) of the served workload's stream (seed
+    1507, 10,000 jobs: n in [10, 26], d in [3, 10], all four orderings)
+    through an 8-team server with a 16 MiB arena (admission binds; wide jobs
+    run GPU-wide), each result against the oracle's digest."""
+    import hashlib
+    exp = load_served_digests()
+    triples = sorted({(n, d, o) for _, n, d, o in workloads.served_jobs(seed=1507, count=10000, rate=1.0)},
+                     key=lambda t: (-t[0], t[1], t[2]))
+    keys = [f"{n}_{d}_{o}" for n, d, o in triples]
+    assert set(keys) == set(exp), "tests/golden/expected_served.txt does not match the served stream"
+    log(f"[served] {len(triples)} distinct triples, {sum(t[0] > 20 for t in triples)} with n > 20")
+    got, waited = {}, 0
+    with gc.Server(arena_bytes=16 << 20, teams=8) as srv:
+        open_tickets = {srv.submit(n, d, o): k for (n, d, o), k in zip(triples, keys)}
+        deadline = time.time() + 300
+        while open_tickets and time.time() < deadline:
+            for tk in list(open_tickets):
+                st, _ = srv.poll(tk)
+                waited += st == gc.GC_JOB_WAITING
+                if st >= gc.GC_JOB_DONE:
+                    w = srv.fetch(tk)
+                    got[open_tickets.pop(tk)] = (len(w), hashlib.sha256(w.astype("<u4").tobytes()).hexdigest())
+                    srv.release(tk)
+            time.sleep(0.0005)
+        assert not open_tickets, f"{len(open_tickets)} jobs unfinished"
+    assert waited > 0
+    bad = [k for k in keys if got[k] != exp[k]]
+    assert not bad, f"served results differ from the oracle for {bad[:10]}"
+
+
+def test_server_wait_expiry_fails_jobs_and_drains():
+    """With a zero spin limit every device-side wait expires at once: the
+    server's jobs must end FAILED with GC_ETIMEOUT, drain must return, and the
+    server must refuse further jobs (no endless relaunch)."""
+    os.environ["GC_SPIN_LIMIT"] = "0"
+    try:
+        with gc.Server(arena_bytes=16 << 20, teams=4) as srv:
+            jobs = [(14, 3, "lex"), (13, 4, "gray"), (12, 5, "grlex")]
+            tickets = [srv.submit(*j) for j in jobs]
+            srv.drain(timeout_ms=60000)
+            states = [srv.poll(t)[0] for t in tickets]
+            assert all(s in (gc.GC_JOB_DONE, gc.GC_JOB_FAILED) for s in states), states
+            assert gc.GC_JOB_FAILED in states
+            for t, j, s in zip(tickets, jobs, states):
+                if s == gc.GC_JOB_FAILED:
+                    with pytest.raises(gc.GreedyCodeError) as e:
+                        srv.fetch(t)
+                    assert e.value.rc == gc.GC_ETIMEOUT
+                else:
+                    assert np.array_equal(srv.fetch(t), ref(*j))
+                srv.release(t)
+            with pytest.raises(gc.GreedyCodeError) as e:
+                srv.submit(10, 3, "lex")
+            assert e.value.rc == gc.GC_ETIMEOUT
+    finally:
+        del os.environ["GC_SPIN_LIMIT"]
+    # the library keeps working afterwards
+    with gc.Server(arena_bytes=16 << 20, teams=4) as srv:
+        t = srv.submit(13, 3, "gray")
+        wait_all(srv, [t])
+        assert np.array_equal(srv.fetch(t), ref(13, 3, "gray"))

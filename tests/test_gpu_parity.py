@@ -141,14 +141,26 @@ def test_repeat_runs_are_identical():
         assert np.array_equal(a, b)
 
 
-def workload_keys(max_n):
-    keys = [k for k in EXPECTED if int(k.split("_")[0]) <= max_n]
+sys.path.insert(0, os.path.join(HERE, "golden"))
+import make_expected  # noqa: E402  (instance list only; the test reads the stored references)
+
+WORKLOAD = [f"{n}_{d}_{o}" for n, d, o in make_expected.instances()]
+
+
+def workload_keys(lo, hi):
+    keys = [k for k in WORKLOAD if lo <= int(k.split("_")[0]) <= hi]
     return sorted(keys, key=lambda k: (int(k.split("_")[0]), k))
 
 
-@pytest.mark.parametrize("key", workload_keys(24))
+def test_every_workload_instance_has_an_oracle_reference():
+    missing = [k for k in WORKLOAD if k not in EXPECTED]
+    assert not missing, f"no oracle reference in expected_codes.txt for {missing}"
+
+
+@pytest.mark.parametrize("key", workload_keys(1, 24))
 def test_workload_instances_up_to_24(key):
     n, d, o = key.split("_")
+    assert key in EXPECTED, f"no oracle reference for {key}"
     m, dig, _, _ = EXPECTED[key]
     t = time.time()
     words, stats = gpu_code(int(n), int(d), o)
@@ -157,9 +169,10 @@ def test_workload_instances_up_to_24(key):
     assert digest(words) == dig
 
 
-@pytest.mark.parametrize("key", [k for k in workload_keys(32) if int(k.split("_")[0]) > 24])
+@pytest.mark.parametrize("key", workload_keys(25, 32))
 def test_workload_instances_large(key):
     n, d, o = key.split("_")
+    assert key in EXPECTED, f"no oracle reference for {key}"
     m, dig, _, _ = EXPECTED[key]
     t = time.time()
     words, stats = gpu_code(int(n), int(d), o)
