@@ -163,6 +163,33 @@ def cpu_baseline(expected, gpu_ms):
                                  f"{gpu_ms.get('26_3_lex')} ms"}
 
 
+def _oracle_time(task):
+    import oracle
+    how, (n, d, o) = task
+    t0 = time.perf_counter()
+    if how == "scan":
+        words, w_ee, _ = oracle.greedy_scan(n, d, oracle.ORDERINGS[o])
+    else:
+        words, w_ee = oracle.greedy_ball(n, d, oracle.ORDERINGS[o], want_w_ee=True)
+    return how, f"{n}_{d}_{o}", time.perf_counter() - t0, len(words), w_ee
+
+
+def oracle_times(expected, workers):
+    """Every screen of the n=24..28 workload on the host CPU, each instance on
+    one thread (`workers` instances at a time): the plain scan (the
+    definition) on the n=24 instances, ball marking on n=26/28 (the scan
+    would take hours there).  Prints one JSON line per instance."""
+    from concurrent.futures import ProcessPoolExecutor
+    tasks = [("scan", i) for i in screens_24_28() if i[0] == 24] + [("ball", i) for i in large_instances()]
+    tasks.sort(key=lambda t: -expected[f"{t[1][0]}_{t[1][1]}_{t[1][2]}"][2])
+    with ProcessPoolExecutor(workers) as ex:
+        for how, key, dt, m, w_ee in ex.map(_oracle_time, tasks):
+            ok = m == expected[key][0] and w_ee == expected[key][2]
+            print(json.dumps({"instance": key, "algorithm": how, "cpu_s": round(dt, 3), "threads": 1,
+                              "checks_per_s": round(w_ee / dt, 1), "matches_reference": ok,
+                              "cpu": cpu_model()}), flush=True)
+
+
 class LaunchLog:
     """Kernel time and algorithmic checks of every timed greedy_code_kernel
     launch, and each instance's launch times."""
@@ -431,6 +458,9 @@ def main():
     ap.add_argument("--served-teams", type=int, default=8)
     ap.add_argument("--served-load", type=float, default=0.7)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
+    ap.add_argument("--oracle-times", type=int, default=0, metavar="WORKERS",
+                    help="only time the CPU oracle on every screen instance (one thread each, "
+                         "WORKERS at a time) and exit")
     ap.add_argument("--host-api", action="store_true",
                     help="also time one step through the host-memory entry point")
     args = ap.parse_args()
@@ -438,6 +468,10 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.oracle_times:
+        oracle_times(load_expected(), args.oracle_times)
+        return
 
     import torch
     import paper_1507_05398_amd as gc

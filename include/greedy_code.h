@@ -15,7 +15,7 @@
  * paper's strings, e.g. "011") is bit n-1, x_n is bit 0.
  *
  * Orderings (section "Ordering Implementation"; the paper names them, the
- * definitions are fixed here):
+ * definitions are fixed here; GC_BORDER is described with gc_problem):
  *   GC_LEX      position p holds the word with value p (Example 1's listing).
  *   GC_GRAY     binary-reflected Gray code, p XOR (p >> 1).
  *   GC_GRLEX    weight ascending; equal weights by increasing value.
@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-enum { GC_LEX = 0, GC_GRAY = 1, GC_GRLEX = 2, GC_GREVLEX = 3 };
+enum { GC_LEX = 0, GC_GRAY = 1, GC_GRLEX = 2, GC_GREVLEX = 3, GC_BORDER = 4 };
 
 enum {
     GC_OK = 0,
@@ -119,6 +119,78 @@ int greedy_code_device(int n, int d, int ordering, uint32_t *d_words, uint64_t c
 int greedy_code_device_ex(int n, int d, int ordering, uint32_t *d_words, uint64_t capacity,
                           uint64_t *d_count, void *hip_stream, const gc_tuning *tuning,
                           gc_stats *stats);
+
+/* The paper's other problems, with the same greedy rule and the same
+ * guarantees (the result is the unique greedy list, bit for bit):
+ *
+ *   ordering GC_BORDER (section "B-ordering Implementation"): an ordered
+ *     basis b_1 .. b_n of F_2^n lists the vectors as 0, b_1, b_2, b_2+b_1,
+ *     b_3, ...: position p holds the XOR of b_{j+1} over the set bits j of p
+ *     (LEX is the basis b_{j+1} = 2^j, GRAY the basis 1, 3, 6, 12, ...).
+ *   weight w >= 0 (section "Brief overview of the Greedy Algorithm and
+ *     Codes": constant-weight codes): only the vectors of weight w are
+ *     candidates, in increasing value (GC_LEX or GC_GRLEX) or in the graded
+ *     reverse lexicographic order (GC_GREVLEX).
+ *   self_orthogonal = 1 (section "Self Orthogonal Greedy Codes
+ *     Implementation"): a candidate is accepted only if it has even weight
+ *     and an even number of ones in common (popcount of the AND) with every
+ *     accepted word, besides distance >= d; the candidates are the
+ *     even-weight vectors of the ordering, in its order.
+ *   start, stop, prefix (checkpoint and resume): only positions [start,
+ *     stop) of the walk are screened (stop 0 = its end), and the code buffer
+ *     already holds the `prefix` words the greedy accepted before `start`
+ *     (what a call that stopped at `start` returned).  Screening [0, P) and
+ *     then [P, end) with the first call's words as prefix gives exactly the
+ *     code of one call over [0, end).
+ *
+ * Rules: n in [1, 32]; the basis (GC_BORDER only; entries past n ignored)
+ * must be linearly independent with every b_j < 2^n; a weight needs GC_LEX,
+ * GC_GRLEX or GC_GREVLEX; self_orthogonal cannot be combined with
+ * GC_BORDER; start <= stop <= the walk's length (gc_problem_positions);
+ * otherwise GC_EINVAL.  A self-orthogonal problem with an odd weight has no
+ * candidates (its code is the prefix). */
+typedef struct gc_problem {
+    int n, d, ordering;      /* ordering: GC_LEX .. GC_GREVLEX, or GC_BORDER */
+    int weight;              /* -1: every weight; w in [0, n]: constant weight w */
+    int self_orthogonal;     /* 0 or 1 */
+    uint32_t basis[32];      /* GC_BORDER: b_1 .. b_n in basis[0 .. n) */
+    uint64_t start, stop;    /* screened positions [start, stop); stop 0 = the end */
+    uint64_t prefix;         /* words already in the output buffer */
+} gc_problem;
+
+/* Fill *p with the plain problem (n, d, ordering): every weight, not
+ * self-orthogonal, the whole walk, no prefix, zero basis.  GC_EINVAL for a
+ * NULL p. */
+int gc_problem_init(gc_problem *p, int n, int d, int ordering);
+
+/* Number of positions of the walk (candidates): 2^n, 2^(n-1) if
+ * self-orthogonal, C(n, w) with a weight (0 if self-orthogonal and w odd).
+ * 0 for an invalid problem. */
+uint64_t gc_problem_positions(const gc_problem *p);
+
+/* Capacity (words, prefix included) that always suffices: the sphere-packing
+ * bound of greedy_code_capacity; with a weight the Johnson bound
+ * A(n, 2e, w) <= floor(n/w * A(n-1, 2e, w-1)) (2e = d rounded up to even:
+ * two words of one weight are at even distance), 1 once w < e; if
+ * self-orthogonal also 2^floor(n/2) (the span of the code is a
+ * self-orthogonal code, of dimension at most n/2); never more than
+ * prefix + the number of positions screened.  0 for an invalid problem. */
+uint64_t gc_problem_capacity(const gc_problem *p);
+
+/* Host-memory entry point of a problem: out_words (caller-owned host array;
+ * *out_count on input = its capacity in words) holds the prefix words on
+ * input and the whole code (prefix first) on return, *out_count = its size.
+ * Runs on the null stream.  GC_ECAPACITY: *out_count = gc_problem_capacity. */
+int greedy_code_problem(const gc_problem *p, uint32_t *out_words, uint64_t *out_count);
+
+/* Device-memory entry point of a problem: d_words (device array of
+ * `capacity` uint32, 16-byte aligned, holding the prefix words) receives the
+ * code after the prefix, *d_count (device uint64) its total size; tuning and
+ * stats as in greedy_code_device_ex (may be NULL).  Errors as in
+ * greedy_code_device. */
+int greedy_code_problem_device(const gc_problem *p, uint32_t *d_words, uint64_t capacity,
+                               uint64_t *d_count, void *hip_stream, const gc_tuning *tuning,
+                               gc_stats *stats);
 
 /* One code of a batch.  Inputs: n, d, ordering, d_words (device array of
  * `capacity` uint32, 16-byte aligned, caller-owned), d_count (device uint64 or

@@ -11,8 +11,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBRARY = os.path.join(HERE, "libgreedy_code.so")
 
-GC_LEX, GC_GRAY, GC_GRLEX, GC_GREVLEX = 0, 1, 2, 3
-ORDERINGS = {"lex": GC_LEX, "gray": GC_GRAY, "grlex": GC_GRLEX, "grevlex": GC_GREVLEX}
+GC_LEX, GC_GRAY, GC_GRLEX, GC_GREVLEX, GC_BORDER = 0, 1, 2, 3, 4
+ORDERINGS = {"lex": GC_LEX, "gray": GC_GRAY, "grlex": GC_GRLEX, "grevlex": GC_GREVLEX, "border": GC_BORDER}
 GC_OK, GC_EINVAL, GC_ECAPACITY, GC_EDEVICE, GC_ENOMEM, GC_ETIMEOUT, GC_EBUSY = 0, -1, -2, -3, -4, -5, -6
 ERROR_NAMES = {GC_EINVAL: "GC_EINVAL", GC_ECAPACITY: "GC_ECAPACITY", GC_EDEVICE: "GC_EDEVICE",
                GC_ENOMEM: "GC_ENOMEM", GC_ETIMEOUT: "GC_ETIMEOUT", GC_EBUSY: "GC_EBUSY"}
@@ -20,6 +20,8 @@ GC_JOB_WAITING, GC_JOB_ADMITTED, GC_JOB_DONE, GC_JOB_FAILED = 0, 1, 2, 3
 
 # Every symbol declared in include/greedy_code.h.
 EXPORTS = ["greedy_code_capacity", "greedy_code", "greedy_code_device", "greedy_code_device_ex",
+           "gc_problem_init", "gc_problem_positions",
+           "gc_problem_capacity", "greedy_code_problem", "greedy_code_problem_device",
            "greedy_code_batch", "greedy_code_tune", "greedy_code_tune_reset",
            "greedy_code_batch_tune", "gc_batch_graph_create", "gc_batch_graph_launch",
            "gc_batch_graph_results", "gc_batch_graph_destroy", "gc_server_create", "gc_server_submit", "gc_server_poll",
@@ -49,6 +51,13 @@ class GcTuning(ctypes.Structure):
     _fields_ = [("near_depth", ctypes.c_uint64), ("target_survivors", ctypes.c_uint32),
                 ("grid_blocks", ctypes.c_uint32), ("resolve_mode", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32)]
+
+
+class GcProblem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("d", ctypes.c_int), ("ordering", ctypes.c_int),
+                ("weight", ctypes.c_int), ("self_orthogonal", ctypes.c_int),
+                ("basis", ctypes.c_uint32 * 32), ("start", ctypes.c_uint64), ("stop", ctypes.c_uint64),
+                ("prefix", ctypes.c_uint64)]
 
 
 class GcJob(ctypes.Structure):
@@ -82,6 +91,18 @@ def load():
                                           ctypes.c_uint64, vp, vp, ctypes.POINTER(GcTuning),
                                           ctypes.POINTER(GcStats)]
     lib.greedy_code_device_ex.restype = ctypes.c_int
+    pp = ctypes.POINTER(GcProblem)
+    lib.gc_problem_init.argtypes = [pp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.gc_problem_init.restype = ctypes.c_int
+    lib.gc_problem_positions.argtypes = [pp]
+    lib.gc_problem_positions.restype = ctypes.c_uint64
+    lib.gc_problem_capacity.argtypes = [pp]
+    lib.gc_problem_capacity.restype = ctypes.c_uint64
+    lib.greedy_code_problem.argtypes = [pp, u32p, u64p]
+    lib.greedy_code_problem.restype = ctypes.c_int
+    lib.greedy_code_problem_device.argtypes = [pp, vp, ctypes.c_uint64, vp, vp, ctypes.POINTER(GcTuning),
+                                               ctypes.POINTER(GcStats)]
+    lib.greedy_code_problem_device.restype = ctypes.c_int
     lib.greedy_code_batch.argtypes = [ctypes.POINTER(GcJob), ctypes.c_int, ctypes.c_int, vp,
                                       ctypes.POINTER(ctypes.c_float)]
     lib.greedy_code_batch.restype = ctypes.c_int
@@ -198,6 +219,82 @@ def device_code(n: int, d: int, ordering, device="cuda", **tuning):
     words = torch.empty(cap, dtype=torch.int32, device=device)
     count = torch.zeros(1, dtype=torch.int64, device=device)
     stats = greedy_code_device_ex(n, d, ordering, words, count, **tuning)
+    m = int(count.item())
+    return words[:m], stats
+
+
+def problem(n: int, d: int, ordering, weight: int = -1, self_orthogonal: bool = False, basis=None,
+            start: int = 0, stop: int = 0, prefix: int = 0) -> GcProblem:
+    """A gc_problem: ordering (name or GC_*; "border" needs `basis` = b_1..b_n),
+    constant weight (-1: all weights), self-orthogonality, and the screened
+    position range [start, stop) after `prefix` words (stop 0 = the end)."""
+    p = GcProblem()
+    _check(load().gc_problem_init(ctypes.byref(p), n, d, _ordering(ordering)))
+    p.weight = int(weight)
+    p.self_orthogonal = int(bool(self_orthogonal))
+    if basis is not None:
+        b = [int(v) for v in basis]
+        if len(b) > 32:
+            raise ValueError("at most 32 basis vectors")
+        for j, v in enumerate(b):
+            p.basis[j] = v
+    p.start, p.stop, p.prefix = int(start), int(stop), int(prefix)
+    return p
+
+
+def problem_positions(p: GcProblem) -> int:
+    """Number of candidates of the problem's walk (0 if the problem is invalid)."""
+    return int(load().gc_problem_positions(ctypes.byref(p)))
+
+
+def problem_capacity(p: GcProblem) -> int:
+    """Capacity in words (prefix included) that always suffices (0 if invalid)."""
+    return int(load().gc_problem_capacity(ctypes.byref(p)))
+
+
+def greedy_code_problem(p: GcProblem, prefix_words=None, capacity: int = None) -> np.ndarray:
+    """Host-memory entry point of a problem: returns the whole code (the
+    prefix words first) as a uint32 array."""
+    cap = problem_capacity(p) if capacity is None else int(capacity)
+    if cap == 0 and problem_positions(p) == 0 and p.prefix == 0:
+        _check(load().greedy_code_problem(ctypes.byref(p), None, ctypes.byref(ctypes.c_uint64(0))))
+        return np.zeros(0, dtype=np.uint32)
+    out = np.zeros(max(cap, 1), dtype=np.uint32)
+    if p.prefix:
+        out[: p.prefix] = np.asarray(prefix_words, dtype=np.uint32)[: p.prefix]
+    count = ctypes.c_uint64(cap)
+    rc = load().greedy_code_problem(ctypes.byref(p), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                    ctypes.byref(count))
+    _check(rc)
+    return out[: count.value].copy()
+
+
+def greedy_code_problem_device(p: GcProblem, words, count, stream=None, near_depth=0, target_survivors=0,
+                               grid_blocks=0, resolve_mode=0) -> dict:
+    """Device entry point of a problem on torch tensors: ``words`` (capacity =
+    numel, holding the prefix words), ``count`` one-element int64 tensor.
+    Returns the work counters."""
+    tuning = GcTuning(near_depth, target_survivors, grid_blocks, resolve_mode, 0)
+    stats = GcStats()
+    rc = load().greedy_code_problem_device(ctypes.byref(p), ctypes.c_void_p(words.data_ptr()), words.numel(),
+                                           ctypes.c_void_p(count.data_ptr()), _stream_ptr(stream),
+                                           ctypes.byref(tuning), ctypes.byref(stats))
+    _check(rc)
+    return stats.as_dict()
+
+
+def device_problem_code(p: GcProblem, device="cuda", prefix_words=None, **tuning):
+    """Convenience: allocate the output on the device (capacity from the
+    problem), copy the prefix words in, run, return (words tensor trimmed to
+    |C|, stats)."""
+    import torch
+    cap = max(problem_capacity(p), 1)
+    words = torch.zeros(cap, dtype=torch.int32, device=device)
+    if p.prefix:
+        pw = np.asarray(prefix_words, dtype=np.uint32)[: p.prefix].view(np.int32)
+        words[: p.prefix] = torch.from_numpy(pw.copy()).to(device)
+    count = torch.zeros(1, dtype=torch.int64, device=device)
+    stats = greedy_code_problem_device(p, words, count, **tuning)
     m = int(count.item())
     return words[:m], stats
 

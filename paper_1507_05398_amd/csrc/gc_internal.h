@@ -30,6 +30,12 @@ struct Job {
   unsigned long long *count;      // device counter written at completion (may be null)
   uint32_t *host_copy;            // device-visible pinned host array that receives the words
                                   // before `done` is set (may be null)
+  int wclass;                     // 0: every weight is a candidate; w + 1: only weight w
+  int so;                         // 1: self-orthogonal (even weights, even common ones)
+  unsigned long long p_start;     // first position screened
+  unsigned long long p_stop;      // end of the screened positions (0: the walk's end)
+  unsigned long long m_start;     // words already in `code` (accepted before p_start)
+  uint32_t basis[32];             // GC_BORDER: b_1 .. b_n
   // outputs
   unsigned long long out_count;
   unsigned long long windows, rounds, survivors, chk_near, chk_deep, chk_pairs;
@@ -99,7 +105,7 @@ size_t team_workspace_bytes();
 int device_info(int dev, int *cus, int *coop, int *blocks_per_cu);
 // Which kernel symbol a persistent launch uses (same code; separate names in
 // profiles).
-enum class LaunchKind { kSingle, kBatch, kServer };
+enum class LaunchKind { kSingle, kSingleSO, kBatch, kServer };
 
 hipError_t launch_persistent(const Params &P, unsigned int grid, hipStream_t stream, LaunchKind kind);
 hipError_t launch_init(Bar *bar, DevQueue *dq, int reset_queue, hipStream_t stream);

@@ -136,9 +136,18 @@ __host__ __device__ inline TeamWs team_ws(char *base) {
 
 size_t team_workspace_bytes() { return kTeamWsBytes; }
 
+// Candidate walk of a job: which vectors are candidates and in which order.
+struct Walk {
+  int n, ord;
+  int so;                              // self-orthogonal: only even-weight vectors are candidates
+};
+
 struct Tables {
-  uint32_t binom[33][33];              // C(a, b)
-  unsigned long long off[34];          // off[w] = number of words of weight < w
+  union {
+    uint32_t binom[33][33];            // graded orders: C(a, b)
+    uint32_t btab[4][256];             // B-ordering: XOR of the basis vectors selected by a byte of p
+  };
+  unsigned long long off[34];          // graded orders: candidates of the allowed weights below w
 };
 
 // Screen tile: code segment (double-buffered), candidate words and ids
@@ -166,11 +175,13 @@ struct Lds {
   uint32_t s1off[kSMax];               // their offsets from the window start
   uint8_t st[kSMax];                   // deep status of each survivor (resolve only)
   Tables tab;
+  Walk walk;
   // job
   int job, n, d, ord, mode;
   uint32_t *code;
   uint32_t *host_copy;                 // server: pinned host copy of the words (or null)
   unsigned long long capacity, total, near_depth;
+  unsigned long long p_start, m_start, classes;
   unsigned int target;
   // window
   unsigned long long p0, m0, w, pe, lo;
@@ -354,13 +365,29 @@ __device__ __forceinline__ uint32_t unrank_weight(const Tables &T, unsigned long
   return x;
 }
 
-__device__ __forceinline__ uint32_t position_word(const Tables &T, int n, int ord, unsigned long long p) {
-  if (ord == GC_LEX) return (uint32_t)p;
-  if (ord == GC_GRAY) return (uint32_t)(p ^ (p >> 1));
+// Word at position p of the walk.  LEX: p.  GRAY: p XOR (p >> 1).  B-ordering
+// (section "B-ordering Implementation"): the XOR of the basis vectors b_{j+1}
+// over the set bits j of p, which lists 0, b_1, b_2, b_2+b_1, b_3, ...; the
+// four bytes of p index four tables of such XORs.  Graded orders (and
+// constant weight, a single allowed class): the weight class of p from the
+// offsets of the allowed classes, then the rank inside the class.
+// Self-orthogonal walks list only the even-weight vectors, in the same
+// order: LEX takes p's bits as the top n-1 coordinates and its parity as the
+// last one; GRAY takes the even positions (the reflected Gray word at q has
+// the weight parity of q); graded walks allow the even classes.
+__device__ __forceinline__ uint32_t position_word(const Tables &T, const Walk &K, unsigned long long p) {
+  if (K.ord == GC_LEX) return K.so ? (uint32_t)((p << 1) | (__builtin_popcountll(p) & 1)) : (uint32_t)p;
+  if (K.ord == GC_GRAY) {
+    const unsigned long long q = K.so ? p << 1 : p;
+    return (uint32_t)(q ^ (q >> 1));
+  }
+  if (K.ord == GC_BORDER)
+    return T.btab[0][p & 255] ^ T.btab[1][(p >> 8) & 255] ^ T.btab[2][(p >> 16) & 255] ^ T.btab[3][(p >> 24) & 255];
+  const int n = K.n;
   int w = 0;
   while (w < n && T.off[w + 1] <= p) ++w;
   const unsigned long long r = p - T.off[w];
-  if (ord == GC_GRLEX) return unrank_weight(T, r, w, n);
+  if (K.ord == GC_GRLEX) return unrank_weight(T, r, w, n);
   // GREVLEX: inside weight w, the r-th word is the bit-reversed complement of
   // the r-th weight-(n-w) integer (complement reverses the increasing order,
   // bit reversal turns "differs first at the top" into "at the bottom").
@@ -369,8 +396,22 @@ __device__ __forceinline__ uint32_t position_word(const Tables &T, int n, int or
   return __builtin_bitreverse32(~y & mask) >> (32 - n);
 }
 
-// Fill the binomial and weight-offset tables for length n (whole workgroup).
-__device__ void init_tables(Tables &T, int n) {
+// Fill the tables of a walk (whole workgroup): binomials and the offsets of
+// the allowed weight classes (bit w of `classes`) for graded walks, the byte
+// tables of the basis for a B-ordering.
+__device__ void init_tables(Tables &T, const Walk &K, unsigned long long classes, const uint32_t *basis) {
+  const int n = K.n;
+  if (K.ord == GC_BORDER) {
+    for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) {
+      const int byte = i >> 8, v = i & 255;
+      uint32_t x = 0;
+      for (int j = 0; j < 8; ++j)
+        if (((v >> j) & 1) && 8 * byte + j < n) x ^= basis[8 * byte + j];
+      T.btab[byte][v] = x;
+    }
+    __syncthreads();
+    return;
+  }
   for (int i = threadIdx.x; i < 33 * 33; i += blockDim.x) {
     const int a = i / 33, b = i % 33;
     // C(a, b) by the multiplicative formula, exact in 64 bits for a <= 32.
@@ -386,7 +427,7 @@ __device__ void init_tables(Tables &T, int n) {
     unsigned long long acc = 0;
     for (int w = 0; w < 34; ++w) {
       T.off[w] = acc;
-      if (w <= n) acc += T.binom[n][w];
+      if (w <= n && ((classes >> w) & 1)) acc += T.binom[n][w];
     }
   }
   __syncthreads();
@@ -401,12 +442,12 @@ __device__ void init_tables(Tables &T, int n) {
 // per id; a set bit means "closer than d to a committed word".
 struct Source {
   const Tables *tab;
-  int n, ord;
+  Walk walk;
   unsigned long long p0;
   const uint32_t *words;  // deep list, or null for window positions
   uint32_t *dead;
   __device__ uint32_t word(uint32_t id) const {
-    return words ? words[id] : position_word(*tab, n, ord, p0 + id);
+    return words ? words[id] : position_word(*tab, walk, p0 + id);
   }
 };
 
@@ -447,15 +488,20 @@ __device__ __forceinline__ unsigned int tile_compact(TileLds &T, int dst, bool k
 // past `live` compare stale entries of the candidate list; the ballot drops
 // them.  The rows' kills are OR-ed into the shared kill masks with LDS
 // atomics that return nothing, so no wave waits on them.
-template <int RG>
+//
+// Self-orthogonal walks (SO) also reject a candidate with an odd number of
+// common ones with a word (section "Self Orthogonal Greedy Codes
+// Implementation"): the OR of the popcounts of the ANDs has bit 0 set.
+template <int RG, bool SO>
 __device__ __forceinline__ void rows_chunk(TileLds &T, int cur, int buf, unsigned int row0,
                                            unsigned int chunk, unsigned int live, uint32_t d) {
   const unsigned int lane = threadIdx.x & 63;
-  uint32_t x[RG], acc0[RG], acc1[RG];
+  uint32_t x[RG], acc0[RG], acc1[RG], odd[RG];
 #pragma unroll
   for (int r = 0; r < RG; ++r) {
     x[r] = T.cw[cur][64u * (row0 + r) + lane];  // row0 + r < kRows
     acc0[r] = acc1[r] = 0xffffffffu;
+    odd[r] = 0;
   }
   const uint4 *sp = reinterpret_cast<const uint4 *>(&T.seg[buf][64 * chunk]);
   uint4 c = sp[0];
@@ -470,13 +516,18 @@ __device__ __forceinline__ void rows_chunk(TileLds &T, int cur, int buf, unsigne
     for (int r = 0; r < RG; ++r) {
       acc0[r] = umin3(acc0[r], dist(x[r], c.x), dist(x[r], c.y));
       acc1[r] = umin3(acc1[r], dist(x[r], c.z), dist(x[r], c.w));
+      if (SO) {
+        odd[r] |= __builtin_popcount(x[r] & c.x) | __builtin_popcount(x[r] & c.y);
+        odd[r] |= __builtin_popcount(x[r] & c.z) | __builtin_popcount(x[r] & c.w);
+      }
     }
     __builtin_amdgcn_sched_barrier(0);
     c = cn;
   }
 #pragma unroll
   for (int r = 0; r < RG; ++r) {
-    const unsigned long long k = ballot(umin(acc0[r], acc1[r]) < d && 64u * (row0 + r) + lane < live);
+    const bool clash = umin(acc0[r], acc1[r]) < d || (SO && (odd[r] & 1u));
+    const unsigned long long k = ballot(clash && 64u * (row0 + r) + lane < live);
     if (lane == 0 && k) __hip_atomic_fetch_or(&T.killw[row0 + r], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 }
@@ -513,12 +564,13 @@ __device__ __forceinline__ unsigned int seg_len_for(unsigned int live, unsigned 
 // when every candidate of the tile is dead.  The tile's dead bits are clear
 // when a screen starts.  Returns the executed checks (candidate slots x
 // words).
+template <bool SO>
 __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint32_t *code, uint32_t id0,
                                           uint32_t nc, unsigned long long a, unsigned long long b,
                                           uint32_t d, unsigned long long *cursor, unsigned int members,
                                           unsigned int blocks, unsigned int far_blocks = 0) {
   TileLds &T = L.u.t;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, wave = tid >> 6;
   const unsigned long long len = b > a ? b - a : 0;
   if (len == 0 || nc == 0) return 0;
   uint32_t *dead = src.dead + (id0 >> 5);  // the tile's 32 dead-bit words
@@ -593,7 +645,10 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
     // 16 waves), and consecutive blocks share a group: every wave gets the
     // same share of the segment.
     const unsigned int rows = (live + 63) / 64, chunks = slen / 64;
-    const unsigned int groups = rows > 8 ? 4u : (rows > 4 ? 2u : 1u);
+    // Self-orthogonal screens keep at most 2 rows per group (their compare
+    // needs a third accumulator per row).
+    const unsigned int groups = SO ? (rows > 8 ? 8u : (rows > 4 ? 4u : (rows > 2 ? 2u : 1u)))
+                                   : (rows > 8 ? 4u : (rows > 4 ? 2u : 1u));
     // A wave's issue priority drops with every block it completes, so the
     // waves of a SIMD progress together and the SIMD still has several waves
     // to interleave when the segment's blocks run out.
@@ -602,10 +657,10 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
     for (unsigned int blk = wave; blk < groups * chunks; blk += kWaves, ++done) {
       const unsigned int g = blk / chunks, chunk = blk % chunks;
       const unsigned int row0 = g * rows / groups, rg = (g + 1) * rows / groups - row0;
-      if (rg == 4) rows_chunk<4>(T, cur, buf, row0, chunk, live, d);
-      else if (rg == 3) rows_chunk<3>(T, cur, buf, row0, chunk, live, d);
-      else if (rg == 2) rows_chunk<2>(T, cur, buf, row0, chunk, live, d);
-      else rows_chunk<1>(T, cur, buf, row0, chunk, live, d);
+      if (!SO && rg == 4) rows_chunk<4, SO>(T, cur, buf, row0, chunk, live, d);
+      else if (!SO && rg == 3) rows_chunk<3, SO>(T, cur, buf, row0, chunk, live, d);
+      else if (rg == 2) rows_chunk<2, SO>(T, cur, buf, row0, chunk, live, d);
+      else rows_chunk<1, SO>(T, cur, buf, row0, chunk, live, d);
       if (done == 0) __builtin_amdgcn_s_setprio(2);
       else if (done == 1) __builtin_amdgcn_s_setprio(1);
       else __builtin_amdgcn_s_setprio(0);
@@ -811,6 +866,7 @@ __device__ void resolve_window(Lds &L, const TeamWs &W) {
 // Building one code with the team
 // ---------------------------------------------------------------------------
 
+template <bool SO>
 __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
   const int tid = threadIdx.x;
   const unsigned int lane = tid & 63;
@@ -848,12 +904,12 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
 
     // ---- A: near screen of [p0, pe0) against code[lo, m0) -----------------
     if (m0 > lo) {
-      const Source src{&L.tab, L.n, L.ord, p0, nullptr, W.win_dead};
+      const Source src{&L.tab, L.walk, p0, nullptr, W.win_dead};
       for_my_tiles(L, (nwin + kTile - 1) / kTile, [&](unsigned long long tile, unsigned int members) {
         const unsigned long long id0 = tile * kTile;
         const uint32_t nc = (uint32_t)(nwin - id0 < (unsigned long long)kTile ? nwin - id0 : kTile);
         const unsigned long long c =
-            tile_screen(L, src, L.code, (uint32_t)id0, nc, lo, m0, d, &W.cur[tile], members,
+            tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, lo, m0, d, &W.cur[tile], members,
                         lo == 0 ? kDeepBlocks : kNearBlocks);
         if (tid == 0) L.cnt_near += c;
       });
@@ -920,7 +976,7 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
       }
       __syncthreads();
       // Words of the survivors, one per thread (graded orders unrank in O(n)).
-      for (unsigned int k = tid; k < L.s; k += kBlock) L.s1w[k] = position_word(L.tab, L.n, L.ord, p0 + L.s1off[k]);
+      for (unsigned int k = tid; k < L.s; k += kBlock) L.s1w[k] = position_word(L.tab, L.walk, p0 + L.s1off[k]);
       __syncthreads();
 
       const unsigned int s = L.s;
@@ -936,7 +992,7 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
         unsigned long long mask = 0;
         for (unsigned int c = 0; c < 64; ++c) {
           const uint32_t y = L.s1w[64 * J + c < s ? 64 * J + c : 0];
-          if (c < cmax && dist(xj, y) < d) mask |= 1ull << c;
+          if (c < cmax && (dist(xj, y) < d || (SO && (__builtin_popcount(xj & y) & 1u)))) mask |= 1ull << c;
         }
         if (j >= s) mask = 0;
         W.adj[64 * (I * (I + 1) / 2) + 64 * J + lane] = mask;
@@ -949,12 +1005,12 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
     const bool deep_now = L.mode == MODE_DEEP_ALL && lo > 0 && L.s > 0;
     if (deep_now) {
       charge(1);
-      const Source src{&L.tab, L.n, L.ord, 0, L.s1w, W.deep_fail};
+      const Source src{&L.tab, L.walk, 0, L.s1w, W.deep_fail};
       for_my_tiles(L, (L.s + kTile - 1) / kTile, [&](unsigned long long tile, unsigned int members) {
         const unsigned long long id0 = tile * kTile;
         const uint32_t nc = (uint32_t)(L.s - id0 < (unsigned long long)kTile ? L.s - id0 : kTile);
         const unsigned long long c =
-            tile_screen(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members,
+            tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members,
                         kDeepBlocks, kFarBlocks);
         if (tid == 0) L.cnt_deep += c;
       });
@@ -978,12 +1034,12 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
       // ---- E: deep scan of the listed survivors against code[0, lo) --------
       {
         const unsigned long long nd = L.ndeep;
-        const Source src{&L.tab, L.n, L.ord, 0, W.deep_word, W.deep_fail};
+        const Source src{&L.tab, L.walk, 0, W.deep_word, W.deep_fail};
         for_my_tiles(L, (nd + kTile - 1) / kTile, [&](unsigned long long tile, unsigned int members) {
           const unsigned long long id0 = tile * kTile;
           const uint32_t nc = (uint32_t)(nd - id0 < (unsigned long long)kTile ? nd - id0 : kTile);
           const unsigned long long c =
-              tile_screen(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members,
+              tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members,
                         kDeepBlocks, kFarBlocks);
           if (tid == 0) L.cnt_deep += c;
         });
@@ -996,16 +1052,18 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
   }
 }
 
-// d = 1: every pair of distinct words is at distance >= 1, so the code is the
-// whole ordering.
+// d = 1 (not self-orthogonal): every pair of distinct words is at distance
+// >= 1, so the code is the walk itself from p_start on.
 __device__ void emit_ordering(Lds &L, const TeamWs &W) {
-  const unsigned long long count = L.total < L.capacity ? L.total : L.capacity;
+  const unsigned long long m0 = L.m_start, avail = L.capacity > m0 ? L.capacity - m0 : 0;
+  const unsigned long long want = L.total > L.p_start ? L.total - L.p_start : 0;
+  const unsigned long long count = want < avail ? want : avail;
   const unsigned long long stride = (unsigned long long)L.team_size * kBlock;
-  for (unsigned long long p = (unsigned long long)L.team_rank * kBlock + threadIdx.x; p < count; p += stride)
-    L.code[p] = position_word(L.tab, L.n, L.ord, p);
+  for (unsigned long long k = (unsigned long long)L.team_rank * kBlock + threadIdx.x; k < count; k += stride)
+    L.code[m0 + k] = position_word(L.tab, L.walk, L.p_start + k);
   if (L.team_rank == 0 && threadIdx.x == 0) {
-    W.ctl->m = count;
-    if (count < L.total) set_status(W.ctl, GC_ECAPACITY);
+    W.ctl->m = m0 + count;
+    if (count < want) set_status(W.ctl, GC_ECAPACITY);
   }
 }
 
@@ -1045,6 +1103,7 @@ __device__ int claim_job(const Params &P) {
 
 // Body of the persistent kernel: the team claims jobs until the queue is empty
 // (batch), the host shuts it down or it stays idle too long (server).
+template <bool SO>
 __device__ __forceinline__ void persistent_body(Lds &L, const Params &P) {
   const int tid = threadIdx.x;
   team_join(L, P);
@@ -1088,15 +1147,32 @@ __device__ __forceinline__ void persistent_body(Lds &L, const Params &P) {
                     : (graded ? kDefaultTarget : kDefaultTargetLinear);
       L.code = ld_sys(&J->code);
       L.capacity = ld_sys(&J->capacity);
-      L.total = 1ull << L.n;
+      const int wclass = ld_sys(&J->wclass);
+      L.walk.n = L.n;
+      L.walk.ord = L.ord;
+      L.walk.so = ld_sys(&J->so);
+      // Allowed weight classes of a graded walk: one class (constant
+      // weight), the even ones (self-orthogonal) or all of them.
+      L.classes = wclass > 0 ? 1ull << (wclass - 1) : (L.walk.so ? 0x5555555555555555ull : ~0ull);
+      L.p_start = ld_sys(&J->p_start);
+      L.m_start = ld_sys(&J->m_start);
+      L.total = ld_sys(&J->p_stop);
       L.cnt_near = L.cnt_deep = L.cnt_pairs = 0;
     }
     __syncthreads();
-    init_tables(L.tab, L.n);
+    init_tables(L.tab, L.walk, L.classes, P.jobs[L.job].basis);
+    if (tid == 0) {
+      // The walk's length: 2^n positions (2^(n-1) self-orthogonal) for the
+      // positional walks, the sizes of the allowed classes for graded ones.
+      const bool positional = L.ord == GC_LEX || L.ord == GC_GRAY || L.ord == GC_BORDER;
+      const unsigned long long len = positional ? (1ull << (L.n - (L.walk.so ? 1 : 0))) : L.tab.off[33];
+      if (L.total == 0 || L.total > len) L.total = len;
+    }
+    __syncthreads();
     if (L.team_rank == 0 && tid == 0) {
       Ctl *c = W.ctl;
-      c->m = 0;
-      c->p = 0;
+      c->m = L.m_start;
+      c->p = L.p_start;
       c->w = kWMin;
       c->status = 0;
       c->action = ACT_NEXT;
@@ -1114,8 +1190,8 @@ __device__ __forceinline__ void persistent_body(Lds &L, const Params &P) {
     if (L.team_rank == 0 && tid < kSMax / 32) W.deep_fail[tid] = 0;
     team_barrier(L, P, P.spin_limit);
 
-    if (L.d <= 1) emit_ordering(L, W);
-    else build_code(L, P, W);
+    if (L.d <= 1 && !L.walk.so) emit_ordering(L, W);
+    else build_code<SO>(L, P, W);
 
     __syncthreads();
     if (tid == 0) {
@@ -1177,17 +1253,24 @@ __device__ __forceinline__ void persistent_body(Lds &L, const Params &P) {
 // launches, the batch launches and the server launches apart.
 __global__ void __launch_bounds__(kBlock) greedy_code_kernel(Params P) {
   __shared__ Lds L;
-  persistent_body(L, P);
+  persistent_body<false>(L, P);
 }
 
 __global__ void __launch_bounds__(kBlock) greedy_batch_kernel(Params P) {
   __shared__ Lds L;
-  persistent_body(L, P);
+  persistent_body<false>(L, P);
 }
 
 __global__ void __launch_bounds__(kBlock) greedy_server_kernel(Params P) {
   __shared__ Lds L;
-  persistent_body(L, P);
+  persistent_body<false>(L, P);
+}
+
+// Self-orthogonal codes: the same body with the extra clash rule compiled in
+// (a kernel of its own, so the plain screen's registers are unaffected).
+__global__ void __launch_bounds__(kBlock) greedy_code_so_kernel(Params P) {
+  __shared__ Lds L;
+  persistent_body<true>(L, P);
 }
 
 // Reset of the barrier block and the device queue before a launch (a kernel
@@ -1261,9 +1344,10 @@ hipError_t launch_init(Bar *bar, DevQueue *dq, int reset_queue, hipStream_t stre
 hipError_t launch_persistent(const Params &P, unsigned int grid, hipStream_t stream, LaunchKind kind) {
   Params copy = P;
   void *args[] = {&copy};
-  const void *fn = kind == LaunchKind::kSingle  ? (const void *)greedy_code_kernel
-                   : kind == LaunchKind::kBatch ? (const void *)greedy_batch_kernel
-                                                : (const void *)greedy_server_kernel;
+  const void *fn = kind == LaunchKind::kSingle     ? (const void *)greedy_code_kernel
+                   : kind == LaunchKind::kSingleSO ? (const void *)greedy_code_so_kernel
+                   : kind == LaunchKind::kBatch    ? (const void *)greedy_batch_kernel
+                                                   : (const void *)greedy_server_kernel;
   return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream);
 }
 
@@ -1486,6 +1570,126 @@ int job_result(const Job &J, uint64_t capacity) {
   return GC_OK;
 }
 
+// ---- generalized problems -------------------------------------------------
+
+// Number of positions of a problem's walk (its candidates).
+uint64_t positions_of(const gc_problem &p) {
+  if (p.weight >= 0) return p.self_orthogonal && (p.weight & 1) ? 0 : binom_host(p.n, p.weight);
+  return 1ull << (p.n - (p.self_orthogonal ? 1 : 0));
+}
+
+// Johnson bound A(n, 2e, w) <= floor(n / w * A(n - 1, 2e, w - 1)), with
+// A(n, 2e, w) = A(n, 2e, n - w) and A = 1 once w < e; never above C(n, w).
+uint64_t johnson_bound(int n, int e, int w) {
+  if (w > n - w) w = n - w;
+  if (w < e) return 1;
+  const uint64_t a = johnson_bound(n - 1, e, w - 1);
+  const uint64_t v = (uint64_t)n * a / (uint64_t)w, c = binom_host(n, w);
+  return v < c ? v : c;
+}
+
+bool problem_plain(const gc_problem &p) {
+  return p.ordering <= GC_GREVLEX && p.weight < 0 && !p.self_orthogonal;
+}
+
+int check_problem(const gc_problem *p) {
+  if (!p) return fail(GC_EINVAL, "problem is NULL");
+  const int n = p->n;
+  if (n < 1 || n > 32) return fail(GC_EINVAL, "n=%d outside [1, 32]", n);
+  if (p->d < 1) return fail(GC_EINVAL, "d=%d must be >= 1", p->d);
+  if (p->ordering < GC_LEX || p->ordering > GC_BORDER) return fail(GC_EINVAL, "unknown ordering %d", p->ordering);
+  if (p->self_orthogonal != 0 && p->self_orthogonal != 1)
+    return fail(GC_EINVAL, "self_orthogonal must be 0 or 1 (got %d)", p->self_orthogonal);
+  if (p->weight < -1 || p->weight > n) return fail(GC_EINVAL, "weight %d outside [-1, %d]", p->weight, n);
+  if (p->weight >= 0 && p->ordering != GC_LEX && p->ordering != GC_GRLEX && p->ordering != GC_GREVLEX)
+    return fail(GC_EINVAL, "a constant weight needs GC_LEX, GC_GRLEX or GC_GREVLEX");
+  if (p->self_orthogonal && p->ordering == GC_BORDER)
+    return fail(GC_EINVAL, "self_orthogonal cannot be combined with GC_BORDER");
+  if (p->ordering == GC_BORDER) {
+    // Independence by elimination: reduce each vector by the pivots so far;
+    // a vector that reduces to zero depends on the earlier ones.
+    uint32_t piv[32] = {0};
+    for (int j = 0; j < n; ++j) {
+      uint32_t v = p->basis[j];
+      if (n < 32 && (v >> n) != 0) return fail(GC_EINVAL, "basis[%d] has bits above n", j);
+      bool placed = false;
+      for (int b = 31; b >= 0 && !placed; --b) {
+        if (!((v >> b) & 1)) continue;
+        if (piv[b]) {
+          v ^= piv[b];
+        } else {
+          piv[b] = v;
+          placed = true;
+        }
+      }
+      if (!placed) return fail(GC_EINVAL, "basis[%d] depends on the earlier basis vectors", j);
+    }
+  }
+  const uint64_t pos = positions_of(*p);
+  const uint64_t stop = p->stop ? p->stop : pos;
+  if (stop > pos) return fail(GC_EINVAL, "stop %llu beyond the walk's %llu positions", (unsigned long long)stop,
+                              (unsigned long long)pos);
+  if (p->start > stop) return fail(GC_EINVAL, "start %llu after stop %llu", (unsigned long long)p->start,
+                                   (unsigned long long)stop);
+  return GC_OK;
+}
+
+uint64_t problem_capacity(const gc_problem &p) {
+  const uint64_t pos = positions_of(p);
+  const uint64_t stop = p.stop ? p.stop : pos, screened = stop - p.start;
+  uint64_t bound;
+  if (p.d <= 1 && !p.self_orthogonal) bound = pos;
+  else if (p.weight >= 0) bound = johnson_bound(p.n, (p.d + 1) / 2, p.weight);
+  else bound = greedy_code_capacity(p.n, p.d);
+  if (p.self_orthogonal && bound > (1ull << (p.n / 2))) bound = 1ull << (p.n / 2);
+  if (bound > p.prefix + screened) bound = p.prefix + screened;
+  return bound > p.prefix ? bound : p.prefix;
+}
+
+void fill_job_problem(Job *J, const gc_problem &p, uint32_t *words, uint64_t capacity, uint64_t *count,
+                      const gc_tuning *tuning) {
+  gc_tuning remembered;
+  if (!tuning && problem_plain(p) && tuned_for(p.n, p.d, p.ordering, &remembered)) tuning = &remembered;
+  memset(J, 0, sizeof(*J));
+  J->n = p.n;
+  J->d = p.d;
+  // One weight class in increasing value is the graded lexicographic walk
+  // restricted to that class.
+  J->ord = p.weight >= 0 && p.ordering == GC_LEX ? GC_GRLEX : p.ordering;
+  J->code = words;
+  J->capacity = capacity;
+  J->count = reinterpret_cast<unsigned long long *>(count);
+  J->wclass = p.weight >= 0 ? p.weight + 1 : 0;
+  J->so = p.self_orthogonal;
+  J->p_start = p.start;
+  J->p_stop = p.stop ? p.stop : positions_of(p);
+  J->m_start = p.prefix;
+  if (p.ordering == GC_BORDER)
+    for (int j = 0; j < p.n; ++j) J->basis[j] = p.basis[j];
+  if (tuning) {
+    J->near_depth = tuning->near_depth;
+    J->target = tuning->target_survivors;
+    J->mode = (int)tuning->resolve_mode;
+  }
+}
+
+void copy_stats(gc_stats *stats, const Job &J, float ms) {
+  if (!stats) return;
+  memset(stats, 0, sizeof(*stats));
+  stats->count = J.out_count;
+  stats->windows = J.windows;
+  stats->resolve_rounds = J.rounds;
+  stats->survivors = J.survivors;
+  stats->checks_near = J.chk_near;
+  stats->checks_deep = J.chk_deep;
+  stats->checks_pairs = J.chk_pairs;
+  stats->kernel_ms = ms;
+  stats->near_ms = J.ticks_near / 1e5;
+  stats->survivors_ms = J.ticks_surv / 1e5;
+  stats->resolve_ms = J.ticks_resolve / 1e5;
+  stats->deep_ms = J.ticks_deep / 1e5;
+}
+
 }  // namespace gcimpl
 
 using namespace gcimpl;
@@ -1511,39 +1715,72 @@ uint64_t greedy_code_capacity(int n, int d) {
   return (1ull << nn) / v;
 }
 
+int gc_problem_init(gc_problem *p, int n, int d, int ordering) {
+  g_error.clear();
+  if (!p) return fail(GC_EINVAL, "problem is NULL");
+  memset(p, 0, sizeof(*p));
+  p->n = n;
+  p->d = d;
+  p->ordering = ordering;
+  p->weight = -1;
+  return GC_OK;
+}
+
+uint64_t gc_problem_positions(const gc_problem *p) {
+  if (check_problem(p)) return 0;
+  return positions_of(*p);
+}
+
+uint64_t gc_problem_capacity(const gc_problem *p) {
+  if (check_problem(p)) return 0;
+  return problem_capacity(*p);
+}
+
+int greedy_code_problem_device(const gc_problem *p, uint32_t *d_words, uint64_t capacity,
+                               uint64_t *d_count, void *hip_stream, const gc_tuning *tuning,
+                               gc_stats *stats) {
+  g_error.clear();
+  int rc = check_problem(p);
+  if (rc) return rc;
+  if (!d_count) return fail(GC_EINVAL, "d_count is NULL");
+  if (!d_words && capacity > 0) return fail(GC_EINVAL, "d_words is NULL");
+  if (((uintptr_t)d_words & 15u) != 0) return fail(GC_EINVAL, "d_words must be 16-byte aligned");
+  if (p->prefix > capacity) return fail(GC_EINVAL, "prefix %llu exceeds the capacity %llu",
+                                        (unsigned long long)p->prefix, (unsigned long long)capacity);
+  if (capacity == 0 && positions_of(*p) > 0) return fail(GC_ECAPACITY, "capacity 0 cannot hold a word");
+  if (tuning && tuning->resolve_mode > 2) return fail(GC_EINVAL, "resolve_mode %u unknown", tuning->resolve_mode);
+  if (stats) memset(stats, 0, sizeof(*stats));
+  hipStream_t stream = (hipStream_t)hip_stream;
+  const uint64_t stop = p->stop ? p->stop : positions_of(*p);
+  if (p->start >= stop) {
+    // Nothing to screen: the code is the prefix.
+    const unsigned long long m = p->prefix;
+    hipError_t e = hipMemcpyAsync(d_count, &m, sizeof(m), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(GC_EDEVICE, "count store failed: %s", hipGetErrorString(e));
+    if (stats) stats->count = m;
+    return GC_OK;
+  }
+  Job J;
+  fill_job_problem(&J, *p, d_words, capacity, d_count, tuning);
+  float ms = 0.f;
+  rc = run_batch(&J, 1, 1, tuning ? tuning->grid_blocks : 0, stream, &ms,
+                 p->self_orthogonal ? LaunchKind::kSingleSO : LaunchKind::kSingle);
+  if (rc) return rc;
+  copy_stats(stats, J, ms);
+  return job_result(J, capacity);
+}
+
 int greedy_code_device_ex(int n, int d, int ordering, uint32_t *d_words, uint64_t capacity,
                           uint64_t *d_count, void *hip_stream, const gc_tuning *tuning,
                           gc_stats *stats) {
   g_error.clear();
   int rc = check_job_args(n, d, ordering);
   if (rc) return rc;
-  if (!d_count) return fail(GC_EINVAL, "d_count is NULL");
-  if (!d_words && capacity > 0) return fail(GC_EINVAL, "d_words is NULL");
-  if (((uintptr_t)d_words & 15u) != 0) return fail(GC_EINVAL, "d_words must be 16-byte aligned");
-  if (capacity == 0) return fail(GC_ECAPACITY, "capacity 0 cannot hold the zero word");
-  if (tuning && tuning->resolve_mode > 2) return fail(GC_EINVAL, "resolve_mode %u unknown", tuning->resolve_mode);
-  if (stats) memset(stats, 0, sizeof(*stats));
-  Job J;
-  fill_job(&J, n, d, ordering, d_words, capacity, d_count, tuning);
-  float ms = 0.f;
-  rc = run_batch(&J, 1, 1, tuning ? tuning->grid_blocks : 0, (hipStream_t)hip_stream, &ms,
-                 LaunchKind::kSingle);
-  if (rc) return rc;
-  if (stats) {
-    stats->count = J.out_count;
-    stats->windows = J.windows;
-    stats->resolve_rounds = J.rounds;
-    stats->survivors = J.survivors;
-    stats->checks_near = J.chk_near;
-    stats->checks_deep = J.chk_deep;
-    stats->checks_pairs = J.chk_pairs;
-    stats->kernel_ms = ms;
-    stats->near_ms = J.ticks_near / 1e5;
-    stats->survivors_ms = J.ticks_surv / 1e5;
-    stats->resolve_ms = J.ticks_resolve / 1e5;
-    stats->deep_ms = J.ticks_deep / 1e5;
-  }
-  return job_result(J, capacity);
+  if (capacity == 0 && d_words) return fail(GC_ECAPACITY, "capacity 0 cannot hold the zero word");
+  gc_problem p;
+  gc_problem_init(&p, n, d, ordering);
+  return greedy_code_problem_device(&p, d_words, capacity, d_count, hip_stream, tuning, stats);
 }
 
 int greedy_code_device(int n, int d, int ordering, uint32_t *d_words, uint64_t capacity,
@@ -1551,28 +1788,34 @@ int greedy_code_device(int n, int d, int ordering, uint32_t *d_words, uint64_t c
   return greedy_code_device_ex(n, d, ordering, d_words, capacity, d_count, hip_stream, nullptr, nullptr);
 }
 
-int greedy_code(int n, int d, int ordering, uint32_t *out_words, uint64_t *out_count) {
+int greedy_code_problem(const gc_problem *p, uint32_t *out_words, uint64_t *out_count) {
   g_error.clear();
   if (!out_count) return fail(GC_EINVAL, "out_count is NULL");
-  const uint64_t bound = greedy_code_capacity(n, d);
-  if (bound == 0) return fail(GC_EINVAL, "invalid n=%d or d=%d", n, d);
-  if (ordering < GC_LEX || ordering > GC_GREVLEX) return fail(GC_EINVAL, "unknown ordering %d", ordering);
+  int rc = check_problem(p);
+  if (rc) return rc;
+  const uint64_t bound = problem_capacity(*p);
   const uint64_t cap = *out_count;
   if (!out_words && cap > 0) return fail(GC_EINVAL, "out_words is NULL");
+  if (p->prefix > cap) return fail(GC_EINVAL, "prefix %llu exceeds the capacity %llu",
+                                   (unsigned long long)p->prefix, (unsigned long long)cap);
   const uint64_t dcap = cap < bound ? cap : bound;
   if (dcap == 0) {
     *out_count = bound;
-    return fail(GC_ECAPACITY, "capacity 0 cannot hold the zero word");
+    if (bound == 0) return GC_OK;  // no candidates and no prefix: the empty code
+    return fail(GC_ECAPACITY, "capacity 0 cannot hold a word");
   }
   uint32_t *dw = nullptr;
   uint64_t *dc = nullptr;
   HIP_TRY(hipMalloc((void **)&dw, dcap * sizeof(uint32_t)));
   hipError_t e = hipMalloc((void **)&dc, sizeof(uint64_t));
+  if (e == hipSuccess && p->prefix)
+    e = hipMemcpy(dw, out_words, p->prefix * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(dw);
-    return fail(GC_ENOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
+    if (dc) (void)hipFree(dc);
+    return fail(GC_ENOMEM, "device buffers: %s", hipGetErrorString(e));
   }
-  int rc = greedy_code_device(n, d, ordering, dw, dcap, dc, nullptr);
+  rc = greedy_code_problem_device(p, dw, dcap, dc, nullptr, nullptr, nullptr);
   if (rc == GC_OK) {
     uint64_t count = 0;
     e = hipMemcpy(&count, dc, sizeof(count), hipMemcpyDeviceToHost);
@@ -1585,6 +1828,16 @@ int greedy_code(int n, int d, int ordering, uint32_t *out_words, uint64_t *out_c
   (void)hipFree(dw);
   (void)hipFree(dc);
   return rc;
+}
+
+int greedy_code(int n, int d, int ordering, uint32_t *out_words, uint64_t *out_count) {
+  g_error.clear();
+  if (!out_count) return fail(GC_EINVAL, "out_count is NULL");
+  int rc = check_job_args(n, d, ordering);
+  if (rc) return rc;
+  gc_problem p;
+  gc_problem_init(&p, n, d, ordering);
+  return greedy_code_problem(&p, out_words, out_count);
 }
 
 int greedy_code_batch(gc_job *jobs, int njobs, int teams, void *hip_stream, float *kernel_ms) {

@@ -134,3 +134,84 @@ def test_empty_batch_is_a_no_op():
     lib = gc.load()
     ms = ctypes.c_float(-1.0)
     assert lib.greedy_code_batch(None, 0, 0, None, ctypes.byref(ms)) == gc.GC_OK
+
+
+# ---- generalized problems (B-ordering, constant weight, self-orthogonal, resume)
+
+def test_problem_positions():
+    assert gc.problem_positions(gc.problem(10, 3, "lex")) == 1024
+    assert gc.problem_positions(gc.problem(10, 3, "grlex", self_orthogonal=True)) == 512
+    assert gc.problem_positions(gc.problem(10, 3, "gray", self_orthogonal=True)) == 512
+    assert gc.problem_positions(gc.problem(10, 4, "lex", weight=3)) == math.comb(10, 3)
+    assert gc.problem_positions(gc.problem(10, 4, "grevlex", weight=4, self_orthogonal=True)) == math.comb(10, 4)
+    assert gc.problem_positions(gc.problem(10, 4, "lex", weight=3, self_orthogonal=True)) == 0
+    basis = [1 << j for j in range(12)]
+    assert gc.problem_positions(gc.problem(12, 3, "border", basis=basis)) == 4096
+
+
+def johnson(n, e, w):
+    w = min(w, n - w)
+    if w < e:
+        return 1
+    return min(n * johnson(n - 1, e, w - 1) // w, math.comb(n, w))
+
+
+def test_problem_capacity_formulas():
+    assert gc.problem_capacity(gc.problem(15, 3, "lex")) == gc.greedy_code_capacity(15, 3)
+    assert gc.problem_capacity(gc.problem(12, 1, "gray")) == 4096
+    assert gc.problem_capacity(gc.problem(16, 6, "lex", weight=5)) == johnson(16, 3, 5) == 48
+    assert gc.problem_capacity(gc.problem(16, 5, "lex", weight=5)) == 48   # odd d: even distances
+    assert gc.problem_capacity(gc.problem(24, 8, "lex", self_orthogonal=True)) == 4096
+    assert gc.problem_capacity(gc.problem(20, 1, "lex", self_orthogonal=True)) == 1024
+    # never more than prefix + screened positions
+    assert gc.problem_capacity(gc.problem(16, 3, "lex", start=100, stop=110, prefix=7)) == 17
+
+
+def test_problem_capacity_holds_the_oracle_codes():
+    """The capacity bound is a bound: every code the oracle builds fits."""
+    import numpy as np
+
+    import oracle
+    for n in range(4, 12):
+        for d in range(1, n + 1):
+            for w in range(0, n + 1, 3):
+                for o in ("lex", "grevlex"):
+                    cand = oracle.weight_class(n, w, oracle.ORDERINGS[o])
+                    words, _, _ = oracle.greedy_list(n, d, cand)
+                    assert len(words) <= gc.problem_capacity(gc.problem(n, d, o, weight=w)), (n, d, w, o)
+            table = oracle.order_table(n, oracle.LEX)
+            words, _, _ = oracle.greedy_list(n, d, table, self_orth=True)
+            assert len(words) <= gc.problem_capacity(gc.problem(n, d, "lex", self_orthogonal=True)), (n, d)
+            assert np.all(np.bitwise_count(words) % 2 == 0)
+
+
+@pytest.mark.parametrize("kw,what", [
+    (dict(n=8, d=3, ordering="gray", weight=3), "constant weight"),
+    (dict(n=8, d=3, ordering="border", weight=3, basis=[1 << j for j in range(8)]), "constant weight"),
+    (dict(n=8, d=3, ordering="border", self_orthogonal=True, basis=[1 << j for j in range(8)]), "self_orthogonal"),
+    (dict(n=8, d=3, ordering="border", basis=[1, 2, 3, 8, 16, 32, 64, 128]), "depends"),
+    (dict(n=8, d=3, ordering="border", basis=[1, 2, 4, 8, 16, 32, 64, 256]), "bits above"),
+    (dict(n=8, d=3, ordering="lex", weight=9), "weight"),
+    (dict(n=8, d=3, ordering="lex", stop=257), "stop"),
+    (dict(n=8, d=3, ordering="lex", start=20, stop=10), "start"),
+])
+def test_problem_validation(kw, what):
+    n, d, o = kw.pop("n"), kw.pop("d"), kw.pop("ordering")
+    p = gc.problem(n, d, o, **kw)
+    assert gc.problem_positions(p) == 0 and gc.problem_capacity(p) == 0
+    assert what in gc.gc_last_error()
+    with pytest.raises(gc.GreedyCodeError) as e:
+        gc.greedy_code_problem(p, capacity=16)
+    assert e.value.rc == gc.GC_EINVAL
+
+
+def test_self_orthogonal_flag_must_be_boolean():
+    p = gc.problem(8, 3, "lex")
+    p.self_orthogonal = 2
+    assert gc.problem_capacity(p) == 0
+
+
+def test_plain_entry_points_reject_border():
+    with pytest.raises(gc.GreedyCodeError) as e:
+        gc.greedy_code(8, 3, "border", capacity=16)
+    assert e.value.rc == gc.GC_EINVAL
