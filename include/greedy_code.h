@@ -192,6 +192,20 @@ int greedy_code_problem_device(const gc_problem *p, uint32_t *d_words, uint64_t 
                                uint64_t *d_count, void *hip_stream, const gc_tuning *tuning,
                                gc_stats *stats);
 
+/* No-allocation variant of greedy_code_device, for callers that cannot
+ * allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and errors as greedy_code_device, but
+ * the call allocates nothing: its device workspace (barrier block, queue, one
+ * job and one team workspace, about 0.9 MiB) is a fixed array that the
+ * library holds on every device it runs on until the process ends, and the
+ * job descriptor reaches the device as a kernel argument.  A launch needs a
+ * fixed workspace size, checked against the array's (GC_EINVAL if it were
+ * larger).  All calls on one device share that array: calls that overlap on
+ * one device (different threads or streams) race and must be serialised by
+ * the caller.  The tuning remembered by greedy_code_tune applies. */
+int greedy_code_device_noalloc(int n, int d, int ordering, uint32_t *d_words, uint64_t capacity,
+                               uint64_t *d_count, void *hip_stream);
+
 /* One code of a batch.  Inputs: n, d, ordering, d_words (device array of
  * `capacity` uint32, 16-byte aligned, caller-owned), d_count (device uint64 or
  * NULL).  Outputs, filled in by greedy_code_batch: status (GC_OK or an error

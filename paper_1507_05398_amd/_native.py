@@ -20,7 +20,7 @@ GC_JOB_WAITING, GC_JOB_ADMITTED, GC_JOB_DONE, GC_JOB_FAILED = 0, 1, 2, 3
 
 # Every symbol declared in include/greedy_code.h.
 EXPORTS = ["greedy_code_capacity", "greedy_code", "greedy_code_device", "greedy_code_device_ex",
-           "gc_problem_init", "gc_problem_positions",
+           "greedy_code_device_noalloc", "gc_problem_init", "gc_problem_positions",
            "gc_problem_capacity", "greedy_code_problem", "greedy_code_problem_device",
            "greedy_code_batch", "greedy_code_tune", "greedy_code_tune_reset",
            "greedy_code_batch_tune", "gc_batch_graph_create", "gc_batch_graph_launch",
@@ -91,6 +91,9 @@ def load():
                                           ctypes.c_uint64, vp, vp, ctypes.POINTER(GcTuning),
                                           ctypes.POINTER(GcStats)]
     lib.greedy_code_device_ex.restype = ctypes.c_int
+    lib.greedy_code_device_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
+                                               ctypes.c_uint64, vp, vp]
+    lib.greedy_code_device_noalloc.restype = ctypes.c_int
     pp = ctypes.POINTER(GcProblem)
     lib.gc_problem_init.argtypes = [pp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.gc_problem_init.restype = ctypes.c_int
@@ -196,6 +199,16 @@ def greedy_code_device(n: int, d: int, ordering, words, count, stream=None) -> N
     rc = load().greedy_code_device(n, d, _ordering(ordering), ctypes.c_void_p(words.data_ptr()),
                                    words.numel(), ctypes.c_void_p(count.data_ptr()),
                                    _stream_ptr(stream))
+    _check(rc)
+
+
+def greedy_code_device_noalloc(n: int, d: int, ordering, words, count, stream=None) -> None:
+    """As greedy_code_device, through the entry point that allocates nothing
+    (its workspace is a fixed device array; overlapping calls on one device
+    race)."""
+    rc = load().greedy_code_device_noalloc(n, d, _ordering(ordering), ctypes.c_void_p(words.data_ptr()),
+                                           words.numel(), ctypes.c_void_p(count.data_ptr()),
+                                           _stream_ptr(stream))
     _check(rc)
 
 

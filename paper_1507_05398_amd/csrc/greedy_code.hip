@@ -1289,6 +1289,29 @@ __global__ void init_kernel(Bar *bar, DevQueue *dq, int reset_queue) {
   }
 }
 
+// Reset of the barrier block and the queue, plus the store of one job passed
+// by value (the no-allocation entry point: no host-to-device copy).
+__global__ void init_job_kernel(Bar *bar, DevQueue *dq, Job *dst, Job job) {
+  const unsigned int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned int nbar = sizeof(Bar) / sizeof(unsigned int);
+  for (unsigned int k = i; k < nbar; k += gridDim.x * blockDim.x) reinterpret_cast<unsigned int *>(bar)[k] = 0;
+  if (i == 0) {
+    dq->claimed = 0;
+    dq->completed = 0;
+    dq->abort = 0;
+    dq->launches = 1;
+    *dst = job;
+  }
+}
+
+// Workspace of greedy_code_device_noalloc: barrier block, queue, one job and
+// one team workspace (about 0.9 MiB), held by every device the library runs
+// on until the process ends.  Host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes =
+    align256(sizeof(Bar)) + align256(sizeof(DevQueue)) + align256(sizeof(Job)) + kTeamWsBytes;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -1570,6 +1593,27 @@ int job_result(const Job &J, uint64_t capacity) {
   return GC_OK;
 }
 
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[64];
+
+int scratch_address(char **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(GC_EDEVICE, "device ordinal %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(GC_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<char *>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return GC_OK;
+}
+
 // ---- generalized problems -------------------------------------------------
 
 // Number of positions of a problem's walk (its candidates).
@@ -1786,6 +1830,42 @@ int greedy_code_device_ex(int n, int d, int ordering, uint32_t *d_words, uint64_
 int greedy_code_device(int n, int d, int ordering, uint32_t *d_words, uint64_t capacity,
                        uint64_t *d_count, void *hip_stream) {
   return greedy_code_device_ex(n, d, ordering, d_words, capacity, d_count, hip_stream, nullptr, nullptr);
+}
+
+int greedy_code_device_noalloc(int n, int d, int ordering, uint32_t *d_words, uint64_t capacity,
+                               uint64_t *d_count, void *hip_stream) {
+  g_error.clear();
+  int rc = check_job_args(n, d, ordering);
+  if (rc) return rc;
+  if (!d_count) return fail(GC_EINVAL, "d_count is NULL");
+  if (!d_words && capacity > 0) return fail(GC_EINVAL, "d_words is NULL");
+  if (((uintptr_t)d_words & 15u) != 0) return fail(GC_EINVAL, "d_words must be 16-byte aligned");
+  if (capacity == 0) return fail(GC_ECAPACITY, "capacity 0 cannot hold the zero word");
+  const LaunchLayout lay = launch_layout(1, 1);
+  if (lay.bytes > kScratchBytes)
+    return fail(GC_EINVAL, "the launch needs %zu bytes of scratch, the library holds %zu", lay.bytes,
+                kScratchBytes);
+  char *base = nullptr;
+  rc = scratch_address(&base);
+  if (rc) return rc;
+  unsigned int grid = 0;
+  rc = pick_grid(0, &grid);
+  if (rc) return rc;
+  Job J;
+  fill_job(&J, n, d, ordering, d_words, capacity, d_count, nullptr);
+  const Params P = launch_params(base, lay, 1, 1);
+  hipStream_t stream = (hipStream_t)hip_stream;
+  hipLaunchKernelGGL(init_job_kernel, dim3(4), dim3(256), 0, stream, P.bar, P.dq, P.jobs, J);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = launch_persistent(P, grid, stream, LaunchKind::kSingle);
+  DevQueue dq;
+  memset(&dq, 0, sizeof(dq));
+  if (e == hipSuccess) e = hipMemcpyAsync(&J, P.jobs, sizeof(Job), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&dq, P.dq, sizeof(dq), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return fail(GC_EDEVICE, "persistent kernel failed: %s", hipGetErrorString(e));
+  if (dq.abort) return fail(GC_ETIMEOUT, "a bounded device-side wait expired");
+  return job_result(J, capacity);
 }
 
 int greedy_code_problem(const gc_problem *p, uint32_t *out_words, uint64_t *out_count) {
