@@ -87,7 +87,11 @@ typedef struct gc_tuning {
     uint32_t resolve_mode;  /* 0 = by ordering, 1 = tentative (deep-scan only the
                                tentatively accepted survivors, repeat until
                                stable), 2 = deep-scan every survivor once */
-    uint32_t reserved;      /* must be 0 */
+    uint32_t deep_tile;     /* candidates per tile of the deep scan: 256, 512 or
+                               1024 (0 = 1024).  The workgroups of a tile sweep
+                               the old code together, newest first; smaller
+                               tiles mean fewer workgroups per sweep, so a
+                               candidate killed deep is dropped sooner. */
 } gc_tuning;
 
 /* Capacity (in words) that always suffices for (n, d): the sphere-packing
@@ -253,10 +257,11 @@ int gc_batch_graph_destroy(gc_batch_graph *graph);
 
 /* Autotuner (no paper counterpart).  Builds (n, d, ordering) once per
  * candidate tuning on `hip_stream` (near-screen depth of the whole code or the
- * newest 65536, 16384 or 4096 words, with either deep-scan policy, then the
- * fastest of those with a larger window), checks that every candidate built
- * the same code word for word, and returns the fastest in *best (its device
- * time in *best_ms, may be NULL).  The choice is remembered per device and
+ * newest 65536, 16384 or 4096 words, with either deep-scan policy; then the
+ * fastest so far with a larger window target, then with deep-scan tiles of 512
+ * and of 256 candidates), checks that every candidate built the same code word
+ * for word, and returns the fastest in *best (its device time in *best_ms, may
+ * be NULL).  The choice is remembered per device and
  * (n, d, ordering): later builds of that instance that pass no tuning
  * (greedy_code, greedy_code_device, greedy_code_device_ex with tuning NULL,
  * batch jobs, server jobs) use it.  Allocates a scratch code buffer

@@ -24,7 +24,7 @@ struct Job {
   int n, d, ord, mode;            // mode: 0 by ordering, 1 tentative, 2 deep-scan all survivors
   unsigned long long near_depth;  // 0: default
   unsigned int target;            // 0: default
-  unsigned int pad0;
+  unsigned int deep_tile;         // candidates per deep-scan tile (0: default)
   uint32_t *code;                 // device array of `capacity` words (16-byte aligned)
   unsigned long long capacity;
   unsigned long long *count;      // device counter written at completion (may be null)

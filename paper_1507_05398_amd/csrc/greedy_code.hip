@@ -111,7 +111,8 @@ struct TeamWs {
 
 constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 constexpr int kNearTiles = (int)(kWMax / kTile);       // tiles of a window
-constexpr int kDeepTiles = (kSMax + kTile - 1) / kTile;  // tiles of a deep list
+constexpr int kMinTile = 256;                          // smallest deep-scan tile (tuning)
+constexpr int kDeepTiles = (kSMax + kMinTile - 1) / kMinTile;  // tiles of a deep list, at most
 constexpr int kCursors = kNearTiles + kDeepTiles;
 constexpr size_t kOffCtl = 0;
 constexpr size_t kOffCur = align256(sizeof(Ctl));
@@ -182,7 +183,7 @@ struct Lds {
   uint32_t *host_copy;                 // server: pinned host copy of the words (or null)
   unsigned long long capacity, total, near_depth;
   unsigned long long p_start, m_start, classes;
-  unsigned int target;
+  unsigned int target, deep_tile;
   // window
   unsigned long long p0, m0, w, pe, lo;
   unsigned int s, s_tot, ndeep, round, tcount, truncated;
@@ -274,7 +275,7 @@ __device__ __forceinline__ bool wait_change(unsigned int *p, unsigned int old, c
 // One-time registration: every workgroup counts itself on its XCD and takes a
 // rank in its team (team = XCD id mod nteams), then all wait until the whole
 // grid has registered.  No assumption is made about the block -> XCD mapping.
-__device__ void team_join(Lds &L, const Params &P) {
+__device__ __forceinline__ void team_join(Lds &L, const Params &P) {
   if (threadIdx.x == 0) {
     Bar *B = P.bar;
     const unsigned int x = xcc_id();
@@ -311,7 +312,7 @@ __device__ void team_join(Lds &L, const Params &P) {
 // device-wide (release), meets the other leaders of the team, acquires, and
 // releases its XCD.  Every workgroup then acquires at agent scope before it
 // reads data written elsewhere.  Waits are bounded by `limit` polls.
-__device__ void team_barrier(Lds &L, const Params &P, unsigned int limit) {
+__device__ __forceinline__ void team_barrier(Lds &L, const Params &P, unsigned int limit) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -564,8 +565,10 @@ __device__ __forceinline__ unsigned int seg_len_for(unsigned int live, unsigned 
 // when every candidate of the tile is dead.  The tile's dead bits are clear
 // when a screen starts.  Returns the executed checks (candidate slots x
 // words).
+// Always inlined: called as a function, its LDS arrays would be reached
+// through generic pointers (measured 15 % slower).
 template <bool SO>
-__device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint32_t *code, uint32_t id0,
+__device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &src, const uint32_t *code, uint32_t id0,
                                           uint32_t nc, unsigned long long a, unsigned long long b,
                                           uint32_t d, unsigned long long *cursor, unsigned int members,
                                           unsigned int blocks, unsigned int far_blocks = 0) {
@@ -573,7 +576,8 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
   const int tid = threadIdx.x, wave = tid >> 6;
   const unsigned long long len = b > a ? b - a : 0;
   if (len == 0 || nc == 0) return 0;
-  uint32_t *dead = src.dead + (id0 >> 5);  // the tile's 32 dead-bit words
+  uint32_t *dead = src.dead + (id0 >> 5);  // the tile's dead-bit words
+  const int dwords = (int)((nc + 31) / 32);
   const unsigned long long share = (len / (2ull * members) + 63) & ~63ull;
   const unsigned int cap = share < 64 ? 64u : (share > (unsigned long long)kSegMax ? (unsigned)kSegMax : (unsigned)share);
   auto claim = [&](unsigned int l) {
@@ -638,7 +642,7 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
     const bool more = next_off < len;
     if (more) fetch(next_off, next_len, buf ^ 1);  // in flight during the compute
     uint32_t seen = 0;
-    if (tid < 32) seen = ld_relaxed(&dead[tid]);  // kills published by the other members
+    if (tid < dwords) seen = ld_relaxed(&dead[tid]);  // kills published by the other members
     // Rows go to 1, 2 or 4 groups of balanced sizes (they differ by at most
     // one; 9..12 rows make 4 groups of 2-3 rather than 3 groups of 4, so that
     // the block count of a segment, groups x chunks, stays a multiple of the
@@ -685,7 +689,7 @@ __device__ unsigned long long tile_screen(Lds &L, const Source &src, const uint3
     // The kills are published after the compaction's first barrier, which
     // also completes the gathering in dloc and the reads of the kill masks.
     live = tile_compact(T, cur ^ 1, keep, word, id, [&] {
-      if (tid < 32) {  // one atomic per dead-bit word
+      if (tid < dwords) {  // one atomic per dead-bit word
         const uint32_t mine = T.dloc[tid];
         if (mine & ~T.dseen[tid]) __hip_atomic_fetch_or(&dead[tid], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
@@ -867,7 +871,7 @@ __device__ void resolve_window(Lds &L, const TeamWs &W) {
 // ---------------------------------------------------------------------------
 
 template <bool SO>
-__device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
+__device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
   const int tid = threadIdx.x;
   const unsigned int lane = tid & 63;
   const uint32_t d = (uint32_t)L.d;
@@ -910,7 +914,7 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
         const uint32_t nc = (uint32_t)(nwin - id0 < (unsigned long long)kTile ? nwin - id0 : kTile);
         const unsigned long long c =
             tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, lo, m0, d, &W.cur[tile], members,
-                        lo == 0 ? kDeepBlocks : kNearBlocks);
+                            lo == 0 ? kDeepBlocks : kNearBlocks);
         if (tid == 0) L.cnt_near += c;
       });
     }
@@ -1006,9 +1010,10 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
     if (deep_now) {
       charge(1);
       const Source src{&L.tab, L.walk, 0, L.s1w, W.deep_fail};
-      for_my_tiles(L, (L.s + kTile - 1) / kTile, [&](unsigned long long tile, unsigned int members) {
-        const unsigned long long id0 = tile * kTile;
-        const uint32_t nc = (uint32_t)(L.s - id0 < (unsigned long long)kTile ? L.s - id0 : kTile);
+      const unsigned int dtile = L.deep_tile;
+      for_my_tiles(L, (L.s + dtile - 1) / dtile, [&](unsigned long long tile, unsigned int members) {
+        const unsigned long long id0 = tile * dtile;
+        const uint32_t nc = (uint32_t)(L.s - id0 < (unsigned long long)dtile ? L.s - id0 : dtile);
         const unsigned long long c =
             tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members,
                         kDeepBlocks, kFarBlocks);
@@ -1035,9 +1040,10 @@ __device__ void build_code(Lds &L, const Params &P, const TeamWs &W) {
       {
         const unsigned long long nd = L.ndeep;
         const Source src{&L.tab, L.walk, 0, W.deep_word, W.deep_fail};
-        for_my_tiles(L, (nd + kTile - 1) / kTile, [&](unsigned long long tile, unsigned int members) {
-          const unsigned long long id0 = tile * kTile;
-          const uint32_t nc = (uint32_t)(nd - id0 < (unsigned long long)kTile ? nd - id0 : kTile);
+        const unsigned int dtile = L.deep_tile;
+        for_my_tiles(L, (nd + dtile - 1) / dtile, [&](unsigned long long tile, unsigned int members) {
+          const unsigned long long id0 = tile * dtile;
+          const uint32_t nc = (uint32_t)(nd - id0 < (unsigned long long)dtile ? nd - id0 : dtile);
           const unsigned long long c =
               tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members,
                         kDeepBlocks, kFarBlocks);
@@ -1147,6 +1153,8 @@ __device__ __forceinline__ void persistent_body(Lds &L, const Params &P) {
                     : (graded ? kDefaultTarget : kDefaultTargetLinear);
       L.code = ld_sys(&J->code);
       L.capacity = ld_sys(&J->capacity);
+      const unsigned int dt = ld_sys(&J->deep_tile);
+      L.deep_tile = dt ? dt : (unsigned int)kTile;
       const int wclass = ld_sys(&J->wclass);
       L.walk.n = L.n;
       L.walk.ord = L.ord;
@@ -1560,6 +1568,7 @@ void fill_job(Job *J, int n, int d, int ordering, uint32_t *words, uint64_t capa
     J->near_depth = tuning->near_depth;
     J->target = tuning->target_survivors;
     J->mode = (int)tuning->resolve_mode;
+    J->deep_tile = tuning->deep_tile;
   }
 }
 
@@ -1714,6 +1723,7 @@ void fill_job_problem(Job *J, const gc_problem &p, uint32_t *words, uint64_t cap
     J->near_depth = tuning->near_depth;
     J->target = tuning->target_survivors;
     J->mode = (int)tuning->resolve_mode;
+    J->deep_tile = tuning->deep_tile;
   }
 }
 
@@ -1793,6 +1803,9 @@ int greedy_code_problem_device(const gc_problem *p, uint32_t *d_words, uint64_t 
                                         (unsigned long long)p->prefix, (unsigned long long)capacity);
   if (capacity == 0 && positions_of(*p) > 0) return fail(GC_ECAPACITY, "capacity 0 cannot hold a word");
   if (tuning && tuning->resolve_mode > 2) return fail(GC_EINVAL, "resolve_mode %u unknown", tuning->resolve_mode);
+  if (tuning && tuning->deep_tile != 0 && tuning->deep_tile != 256 && tuning->deep_tile != 512 &&
+      tuning->deep_tile != 1024)
+    return fail(GC_EINVAL, "deep_tile %u must be 0, 256, 512 or 1024", tuning->deep_tile);
   if (stats) memset(stats, 0, sizeof(*stats));
   hipStream_t stream = (hipStream_t)hip_stream;
   const uint64_t stop = p->stop ? p->stop : positions_of(*p);
@@ -1988,13 +2001,17 @@ int greedy_code_tune(int n, int d, int ordering, void *hip_stream, gc_tuning *be
   float ms = 0.f;
   rc = run(cands[0], &ms, ref);  // warm-up, also the reference output
   ref_m = ref.size();
-  for (size_t i = 0; rc == GC_OK && i <= cands.size(); ++i) {
+  // The listed candidates, then refinements of the fastest so far: a larger
+  // window target, then deep-scan tiles of 512 and 256 candidates.
+  const size_t nrefine = 3;
+  for (size_t i = 0; rc == GC_OK && i < cands.size() + nrefine; ++i) {
     gc_tuning t;
     if (i < cands.size()) {
       t = cands[i];
     } else {
-      t = cands[best_i];
-      t.target_survivors = 1000;
+      t = *best;
+      if (i == cands.size()) t.target_survivors = 1000;
+      else t.deep_tile = i == cands.size() + 1 ? 512 : 256;
     }
     rc = run(t, &ms, cur);
     if (rc) break;
@@ -2004,7 +2021,7 @@ int greedy_code_tune(int n, int d, int ordering, void *hip_stream, gc_tuning *be
     }
     if (best_i < 0 || ms < best_t) {
       best_t = ms;
-      best_i = (int)(i < cands.size() ? i : cands.size());
+      best_i = (int)i;
       *best = t;
     }
   }

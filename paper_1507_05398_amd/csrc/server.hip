@@ -211,6 +211,7 @@ int pump(gc_server *s) {
       J->near_depth = tu.near_depth;
       J->target = tu.target_survivors;
       J->mode = (int)tu.resolve_mode;
+      J->deep_tile = tu.deep_tile;
     }
     s->slot_ticket[t.slot] = id;
     s->inflight.insert(id);

@@ -215,3 +215,11 @@ def test_plain_entry_points_reject_border():
     with pytest.raises(gc.GreedyCodeError) as e:
         gc.greedy_code(8, 3, "border", capacity=16)
     assert e.value.rc == gc.GC_EINVAL
+
+
+def test_tuning_deep_tile_is_validated():
+    lib = gc.load()
+    t = gc._native.GcTuning(0, 0, 0, 0, 300)
+    rc = lib.greedy_code_device_ex(8, 3, 0, ctypes.c_void_p(64), 16, ctypes.c_void_p(64), None,
+                                   ctypes.byref(t), None)
+    assert rc == gc.GC_EINVAL and "deep_tile" in gc.gc_last_error()

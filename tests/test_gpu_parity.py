@@ -97,9 +97,11 @@ def test_host_entry_point():
                                     dict(grid_blocks=1), dict(grid_blocks=7, near_depth=200),
                                     dict(near_depth=300, resolve_mode=1),
                                     dict(near_depth=300, resolve_mode=2),
-                                    dict(grid_blocks=13, near_depth=1, resolve_mode=2)],
+                                    dict(grid_blocks=13, near_depth=1, resolve_mode=2),
+                                    dict(near_depth=100, deep_tile=256),
+                                    dict(near_depth=700, deep_tile=512, resolve_mode=1)],
                          ids=["near1", "near64_t16", "nearall_t1024", "grid1", "grid7",
-                              "tentative", "deepall", "grid13_deepall"])
+                              "tentative", "deepall", "grid13_deepall", "tile256", "tile512_tentative"])
 def test_tuning_does_not_change_the_code(o, tuning):
     for n, d in [(16, 3), (17, 4), (16, 5), (18, 6)]:
         words, _ = gpu_code(n, d, o, **tuning)

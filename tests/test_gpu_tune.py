@@ -31,6 +31,7 @@ def test_tune_then_build_matches_oracle(n, d, o):
     best = gc.greedy_code_tune(n, d, o)
     assert best["ms"] > 0
     assert best["resolve_mode"] in (0, 1, 2)
+    assert best["deep_tile"] in (0, 256, 512)
     ref = oracle.greedy_ball(n, d, oracle.ORDERINGS[o])[0]
     words, _ = gc.device_code(n, d, o)           # no tuning passed: the remembered one
     np.testing.assert_array_equal(words.cpu().numpy().view(np.uint32), ref)
