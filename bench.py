@@ -182,8 +182,10 @@ def oracle_times(expected, workers):
     from concurrent.futures import ProcessPoolExecutor
     tasks = [("scan", i) for i in screens_24_28() if i[0] == 24] + [("ball", i) for i in large_instances()]
     tasks.sort(key=lambda t: -expected[f"{t[1][0]}_{t[1][1]}_{t[1][2]}"][2])
+    from concurrent.futures import as_completed
     with ProcessPoolExecutor(workers) as ex:
-        for how, key, dt, m, w_ee in ex.map(_oracle_time, tasks):
+        for fut in as_completed([ex.submit(_oracle_time, t) for t in tasks]):
+            how, key, dt, m, w_ee = fut.result()
             ok = m == expected[key][0] and w_ee == expected[key][2]
             print(json.dumps({"instance": key, "algorithm": how, "cpu_s": round(dt, 3), "threads": 1,
                               "checks_per_s": round(w_ee / dt, 1), "matches_reference": ok,
@@ -458,6 +460,8 @@ def main():
     ap.add_argument("--served-teams", type=int, default=8)
     ap.add_argument("--served-load", type=float, default=0.7)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
+    ap.add_argument("--probe", action="store_true",
+                    help="only run the measurement probes (block-loop VALU rate, team barrier) and exit")
     ap.add_argument("--oracle-times", type=int, default=0, metavar="WORKERS",
                     help="only time the CPU oracle on every screen instance (one thread each, "
                          "WORKERS at a time) and exit")
@@ -480,6 +484,16 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration(torch, args.copy_calibration)
+        return
+    if args.probe:
+        gc.load()
+        out = {"peak_gchecks_per_s": round(PEAK_GCHECKS, 1)}
+        for k in (1, 2):
+            v = gc.probe_block_loop(wgs_per_cu=k, iters=4096) / 1e9
+            out[f"block_loop_{k}wg_per_cu_gchecks_per_s"] = round(v, 1)
+            out[f"block_loop_{k}wg_per_cu_frac_of_peak"] = round(v / PEAK_GCHECKS, 4)
+        out["team_barrier_us"] = round(gc.probe_barrier(iters=20000), 3)
+        print(json.dumps(out), flush=True)
         return
     gc.load()
     expected = load_expected()

@@ -324,6 +324,18 @@ int gc_server_drain(gc_server *srv, int timeout_ms);
  * abandoned; the kernel finishes the ones it is building first). */
 int gc_server_destroy(gc_server *srv);
 
+/* Measurement probes (no paper counterpart; they measure the machine the
+ * construction runs on).  gc_probe_block_loop runs the screen's block loop
+ * alone (four rows of 64 candidates against broadcast code words: v_xor_b32,
+ * v_bcnt_u32_b32 and v_min3_u32, 2.5 VALU ops per distance check) in
+ * wgs_per_cu (1 or 2) workgroups of 1024 threads per compute unit for
+ * `iters` calls per wave, and returns the distance checks per second.
+ * gc_probe_barrier times `iters` team-wide barriers of the persistent kernel
+ * (one team spanning the GPU) and returns microseconds per barrier.  Both run
+ * on the null stream and synchronize. */
+int gc_probe_block_loop(int wgs_per_cu, int iters, double *checks_per_s);
+int gc_probe_barrier(int iters, double *us_per_barrier);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *gc_last_error(void);
 

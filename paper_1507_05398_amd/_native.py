@@ -24,7 +24,8 @@ EXPORTS = ["greedy_code_capacity", "greedy_code", "greedy_code_device", "greedy_
            "gc_problem_capacity", "greedy_code_problem", "greedy_code_problem_device",
            "greedy_code_batch", "greedy_code_tune", "greedy_code_tune_reset",
            "greedy_code_batch_tune", "gc_batch_graph_create", "gc_batch_graph_launch",
-           "gc_batch_graph_results", "gc_batch_graph_destroy", "gc_server_create", "gc_server_submit", "gc_server_poll",
+           "gc_batch_graph_results", "gc_batch_graph_destroy", "gc_probe_block_loop", "gc_probe_barrier",
+           "gc_server_create", "gc_server_submit", "gc_server_poll",
            "gc_server_words", "gc_server_fetch", "gc_server_stats", "gc_server_release",
            "gc_server_drain", "gc_server_destroy", "gc_last_error", "gc_version"]
 
@@ -145,6 +146,10 @@ def load():
     lib.gc_server_drain.restype = ctypes.c_int
     lib.gc_server_destroy.argtypes = [vp]
     lib.gc_server_destroy.restype = ctypes.c_int
+    lib.gc_probe_block_loop.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.gc_probe_block_loop.restype = ctypes.c_int
+    lib.gc_probe_barrier.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.gc_probe_barrier.restype = ctypes.c_int
     lib.gc_last_error.argtypes = []
     lib.gc_last_error.restype = ctypes.c_char_p
     lib.gc_version.argtypes = []
@@ -349,6 +354,20 @@ def greedy_code_tune(n: int, d: int, ordering, stream=None) -> dict:
 
 def greedy_code_tune_reset() -> None:
     load().greedy_code_tune_reset()
+
+
+def probe_block_loop(wgs_per_cu: int = 1, iters: int = 4096) -> float:
+    """Distance checks per second of the screen's block loop alone."""
+    v = ctypes.c_double()
+    _check(load().gc_probe_block_loop(wgs_per_cu, iters, ctypes.byref(v)))
+    return v.value
+
+
+def probe_barrier(iters: int = 20000) -> float:
+    """Microseconds per team-wide barrier (one team spanning the GPU)."""
+    v = ctypes.c_double()
+    _check(load().gc_probe_barrier(iters, ctypes.byref(v)))
+    return v.value
 
 
 class BatchPlan:

@@ -1321,6 +1321,41 @@ constexpr size_t kScratchBytes =
 static __device__ __align__(256) char scratch[kScratchBytes];
 
 // ---------------------------------------------------------------------------
+// Measurement probes (the roofline's denominator and the barrier latency)
+// ---------------------------------------------------------------------------
+
+// The screen's block loop alone: every wave runs rows_chunk<4> (four rows of
+// 64 candidates against a 64-word chunk) `iters` times on LDS filled with
+// pseudo-random words, with d = 1 so that nothing is killed.  Each call is
+// 16 * 64 lanes * 4 rows * 4 words = 16384 distance checks per wave.
+__global__ void __launch_bounds__(kBlock) probe_block_loop_kernel(int iters, unsigned long long *sink) {
+  __shared__ TileLds T;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  uint32_t h = 2654435761u * (uint32_t)(blockIdx.x * kBlock + tid + 1);
+  for (int i = tid; i < 2 * kSegMax; i += kBlock) {
+    h ^= h << 13; h ^= h >> 17; h ^= h << 5;
+    (&T.seg[0][0])[i] = h;
+  }
+  for (int i = tid; i < 2 * kTile; i += kBlock) {
+    h ^= h << 13; h ^= h >> 17; h ^= h << 5;
+    (&T.cw[0][0])[i] = h;
+  }
+  if (tid < kRows) T.killw[tid] = 0;
+  __syncthreads();
+  for (int it = 0; it < iters; ++it)
+    rows_chunk<4, false>(T, 0, 0, 4u * (wave & 3), (unsigned)(wave + it) & 63u, kTile, 1u);
+  __syncthreads();
+  if (tid == 0) atomicAdd(sink, T.killw[0] + 1ull);
+}
+
+// Team barriers alone: the grid joins one team and crosses `iters` barriers.
+__global__ void __launch_bounds__(kBlock) probe_barrier_kernel(Params P, int iters) {
+  __shared__ Lds L;
+  team_join(L, P);
+  for (int i = 0; i < iters && !L.abort; ++i) team_barrier(L, P, P.spin_limit);
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 
@@ -1931,6 +1966,81 @@ int greedy_code(int n, int d, int ordering, uint32_t *out_words, uint64_t *out_c
   gc_problem p;
   gc_problem_init(&p, n, d, ordering);
   return greedy_code_problem(&p, out_words, out_count);
+}
+
+int gc_probe_block_loop(int wgs_per_cu, int iters, double *checks_per_s) {
+  g_error.clear();
+  if (!checks_per_s || wgs_per_cu < 1 || wgs_per_cu > 2 || iters < 1)
+    return fail(GC_EINVAL, "wgs_per_cu must be 1 or 2, iters >= 1, checks_per_s non-NULL");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  int cus = 0;
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  int per_cu = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, probe_block_loop_kernel, kBlock, 0));
+  if (per_cu < wgs_per_cu) return fail(GC_EINVAL, "only %d probe workgroups fit a compute unit", per_cu);
+  char *ws = nullptr;
+  int slot = -1;
+  int rc = acquire_workspace(256, &ws, &slot);
+  if (rc) return rc;
+  unsigned long long *sink = reinterpret_cast<unsigned long long *>(ws);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const unsigned int grid = (unsigned int)(cus * wgs_per_cu);
+  // warm-up, then the timed launch
+  if (e == hipSuccess) hipLaunchKernelGGL(probe_block_loop_kernel, dim3(grid), dim3(kBlock), 0, nullptr, 8, sink);
+  if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+  if (e == hipSuccess) hipLaunchKernelGGL(probe_block_loop_kernel, dim3(grid), dim3(kBlock), 0, nullptr, iters, sink);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  release_workspace(slot);
+  if (e != hipSuccess) return fail(GC_EDEVICE, "block-loop probe failed: %s", hipGetErrorString(e));
+  const double checks = (double)grid * kWaves * (double)iters * 16384.0;
+  *checks_per_s = checks / (ms * 1e-3);
+  return GC_OK;
+}
+
+int gc_probe_barrier(int iters, double *us_per_barrier) {
+  g_error.clear();
+  if (!us_per_barrier || iters < 1) return fail(GC_EINVAL, "iters >= 1 and us_per_barrier non-NULL");
+  unsigned int grid = 0;
+  int rc = pick_grid(0, &grid);
+  if (rc) return rc;
+  const LaunchLayout lay = launch_layout(0, 1);
+  char *ws = nullptr;
+  int slot = -1;
+  rc = acquire_workspace(lay.bytes, &ws, &slot);
+  if (rc) return rc;
+  Params P = launch_params(ws, lay, 0, 1);
+  Params copy = P;
+  int it = iters;
+  void *args[] = {&copy, &it};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = launch_init(P.bar, P.dq, 1, nullptr);
+  if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+  if (e == hipSuccess)
+    e = hipLaunchCooperativeKernel((const void *)probe_barrier_kernel, dim3(grid), dim3(kBlock), args, 0, nullptr);
+  if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+  DevQueue dq;
+  memset(&dq, 0, sizeof(dq));
+  if (e == hipSuccess) e = hipMemcpy(&dq, P.dq, sizeof(dq), hipMemcpyDeviceToHost);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e == hipSuccess) release_workspace(slot);
+  if (e != hipSuccess) return fail(GC_EDEVICE, "barrier probe failed: %s", hipGetErrorString(e));
+  if (dq.abort) return fail(GC_ETIMEOUT, "a bounded device-side wait expired");
+  *us_per_barrier = ms * 1e3 / iters;
+  return GC_OK;
 }
 
 int greedy_code_batch(gc_job *jobs, int njobs, int teams, void *hip_stream, float *kernel_ms) {
