@@ -421,7 +421,9 @@ def bench_served(gc, njobs, arena_bytes, teams, load_frac):
     span, lat, waits = serve(arrivals)
     q = lambda v, f: v[min(njobs - 1, int(f * njobs))]
     return {"jobs": njobs, "seed": 1507, "arena_bytes": arena_bytes, "teams": teams,
-            "wide_jobs": "2^n * capacity(n, d) >= 2^38: built GPU-wide",
+            "wide_jobs": ("2^n * capacity(n, d) >= 2^38: wide queue, one team of 8 - teams XCDs; "
+                          "other jobs: teams teams of one XCD (and the wide team when idle)"
+                          if teams in (2, 4) else "one queue, equal teams"),
             "serial_makespan_s": round(serial_s, 3), "serial_jobs_per_s": round(njobs / serial_s, 2),
             "burst_makespan_s": round(burst_span, 3), "capacity_jobs_per_s": round(capacity, 2),
             "burst_p99_ms": round(q(burst_lat, 0.99) * 1e3, 3),
@@ -456,8 +458,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-jobs", type=int, default=10000)
-    ap.add_argument("--served-arena-mib", type=int, default=16)
-    ap.add_argument("--served-teams", type=int, default=8)
+    ap.add_argument("--served-arena-mib", type=int, default=32)
+    ap.add_argument("--served-teams", type=int, default=2)
     ap.add_argument("--served-load", type=float, default=0.7)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
     ap.add_argument("--probe", action="store_true",

@@ -284,12 +284,14 @@ int greedy_code_batch_tune(gc_job *jobs, int njobs, void *hip_stream, int *best_
  * for its worst-case code (greedy_code_capacity(n, d) words); admitted jobs
  * go to a queue in pinned host memory that the running kernel's teams pull
  * from, so a job arriving while others build starts as soon as a team frees
- * up.  Jobs run in arrival order.  With more than one team, a job whose
- * exhaustive work bound 2^n * greedy_code_capacity(n, d) is at least 2^38
- * ("wide") is built by a launch whose single team spans the GPU, and the
- * other jobs by the narrow teams: a launch stops claiming at the first job
- * of the other kind and the server relaunches with the shape that job needs.
- * Finished codes stay resident in the arena until released.  The kernel
+ * up.  With teams 2 or 4, a job whose exhaustive work bound
+ * 2^n * greedy_code_capacity(n, d) is at least 2^38 ("wide") goes to a wide
+ * queue, served by one team spanning 8 - teams of the eight XCDs; the other
+ * jobs go to a narrow queue, served by `teams` teams of one XCD each and by
+ * the wide team whenever no wide job waits.  Each queue runs in arrival
+ * order; narrow jobs never wait behind a wide one, and may be admitted past a
+ * wide job that waits for arena space until it has waited 1 s.  Finished
+ * codes stay resident in the arena until released.  The kernel
  * exits after about 0.1 s without work and is relaunched on demand.  If a
  * bounded device-side wait expires, every unfinished job fails with
  * GC_ETIMEOUT (gc_server_poll reports GC_JOB_FAILED) and the server accepts
@@ -300,8 +302,9 @@ typedef struct gc_server gc_server;
 /* arena_bytes: device memory for resident codes (the server also allocates
  * as much pinned host memory: each finished code is written there by the
  * kernel itself, so fetching a result needs no device copy while the kernel
- * holds the GPU); teams: narrow teams, 1, 2, 4 or 8 (1: every job on one
- * team spanning the GPU). */
+ * holds the GPU); teams: 1 (one team spanning the GPU) or 8 (one team per
+ * XCD): every job in one queue, in arrival order; 2 or 4: the wide team of
+ * 8 - teams XCDs plus `teams` narrow teams of one XCD. */
 int gc_server_create(size_t arena_bytes, int teams, gc_server **out);
 /* Queue a job; *ticket identifies it.  GC_ENOMEM if its worst-case code can
  * never fit the arena. */

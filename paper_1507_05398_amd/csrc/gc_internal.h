@@ -43,23 +43,25 @@ struct Job {
   unsigned long long t_claim, t_done;  // device wall clock (100 MHz) at claim / completion
   int status;
   unsigned int done;              // 0 pending, 1 finished (written last)
-  int wide;                       // server: built only by a launch whose one team spans the GPU
+  int wide;                       // server: queued on the wide ring
 };
 
 // Job queue.  `submitted` and `shutdown` may live in host memory (server);
 // `claimed` and `abort` always live in device memory.
 struct HostQueue {
-  unsigned int submitted;   // number of jobs visible to the device
+  unsigned int submitted;   // batch: jobs visible to the device; server: entries of the narrow ring
   unsigned int shutdown;    // host sets 1: the kernel exits when idle
-  unsigned int pad[62];
+  unsigned int submitted_wide;  // server: entries of the wide ring
+  unsigned int pad[61];
 };
 
 struct DevQueue {
-  unsigned int claimed;     // next job index to claim
+  unsigned int claimed;     // next job (batch) or narrow-ring entry (server) to claim
   unsigned int completed;   // jobs finished
   int abort;                // a bounded wait expired: every team stops
   unsigned int launches;
-  unsigned int pad[60];
+  unsigned int claimed_wide;  // server: next wide-ring entry to claim
+  unsigned int pad[59];
 };
 
 // Per-team instance state.
@@ -93,8 +95,14 @@ struct Params {
   Bar *bar;
   int njobs_fixed;               // batch: number of jobs; server: -1 (read hq->submitted)
   int nteams;
-  int claim_kind;                // server: 0 claims every job, 1 only narrow jobs, 2 only wide
-                                 // jobs (a team stops at the first job of the other kind)
+  // Server split: team 0 is the XCDs whose id mod 8 is below `split` and
+  // claims from the wide ring first, then the narrow ring; each other XCD is
+  // one of the teams 1 .. nteams-1, which claim from the narrow ring only.
+  // 0: teams are XCD id mod nteams and claim one queue (batch, or a one-team
+  // server).
+  int split;
+  unsigned int *ring;            // server: job indices in publication order (narrow jobs)
+  unsigned int *ring_wide;       // server: job indices of the wide jobs
   unsigned int spin_limit;       // bounded waits inside a job
   unsigned int idle_limit;       // server: polls of an empty queue before the kernel exits
   char *team_ws;                 // per-team workspace, team_ws_stride bytes each

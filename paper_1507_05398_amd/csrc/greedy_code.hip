@@ -272,14 +272,22 @@ __device__ __forceinline__ bool wait_change(unsigned int *p, unsigned int old, c
 // Teams and barriers
 // ---------------------------------------------------------------------------
 
+// Team of an XCD: XCD id mod nteams, or with the server's split the wide
+// team 0 for ids below `split` (mod 8) and one narrow team per other XCD.
+__device__ __forceinline__ unsigned int team_of(const Params &P, unsigned int x) {
+  if (!P.split) return x % (unsigned int)P.nteams;
+  const unsigned int r = x & 7u, w = (unsigned int)P.split;
+  return r < w ? 0u : 1u + (r - w) % (unsigned int)(P.nteams - 1);
+}
+
 // One-time registration: every workgroup counts itself on its XCD and takes a
-// rank in its team (team = XCD id mod nteams), then all wait until the whole
-// grid has registered.  No assumption is made about the block -> XCD mapping.
+// rank in its team, then all wait until the whole grid has registered.  No
+// assumption is made about the block -> XCD mapping.
 __device__ __forceinline__ void team_join(Lds &L, const Params &P) {
   if (threadIdx.x == 0) {
     Bar *B = P.bar;
     const unsigned int x = xcc_id();
-    const unsigned int t = x % (unsigned int)P.nteams;
+    const unsigned int t = team_of(P, x);
     __hip_atomic_fetch_add(&B->xcd[x][2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned int rank =
         __hip_atomic_fetch_add(&B->team[t][2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -295,7 +303,7 @@ __device__ __forceinline__ void team_join(Lds &L, const Params &P) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     unsigned int nx = 0;
     for (int i = 0; i < kMaxXcd; ++i)
-      if ((unsigned int)i % (unsigned int)P.nteams == t && ld_relaxed(&B->xcd[i][2]) > 0) ++nx;
+      if (team_of(P, (unsigned int)i) == t && ld_relaxed(&B->xcd[i][2]) > 0) ++nx;
     L.xcd = x;
     L.xcd_members = ld_relaxed(&B->xcd[x][2]);
     L.team = t;
@@ -1079,29 +1087,36 @@ __device__ void emit_ordering(Lds &L, const TeamWs &W) {
 
 // Claim the next job (team rank 0, thread 0).  Batch: a fixed count.  Server:
 // wait (bounded by idle_limit polls) until the host publishes one, or stop
-// when the host asks for shutdown.  Returns -1 when the team should stop.
-__device__ int claim_job(const Params &P) {
+// when the host asks for shutdown; with the split, team 0 takes the oldest
+// wide job first and the other teams only narrow ones.  Returns -1 when the
+// team should stop.
+__device__ int claim_job(const Params &P, unsigned int team) {
   if (P.njobs_fixed >= 0) {
     const unsigned int j =
         __hip_atomic_fetch_add(&P.dq->claimed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return j < (unsigned int)P.njobs_fixed ? (int)j : -1;
   }
+  // Claim the next entry of a ring whose published count lives in host memory.
+  auto take = [&](unsigned int *submitted, unsigned int *claimed, unsigned int *ring, int *out) {
+    // Acquire: the entries and job descriptors the host published first.
+    const unsigned int sub = __hip_atomic_load(submitted, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+    unsigned int c = ld_relaxed(claimed);
+    while (c < sub) {
+      if (__hip_atomic_compare_exchange_strong(claimed, &c, c + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)) {
+        *out = (int)ld_sys(&ring[c]);
+        return true;
+      }
+    }
+    return false;
+  };
   unsigned int idle = 0;
   for (;;) {
     if (ld_relaxed(&P.dq->abort)) return -1;
     if (ld_sys(&P.hq->shutdown)) return -1;  // outstanding jobs are abandoned
-    // Acquire: the job descriptors the host published before `submitted`.
-    const unsigned int sub = __hip_atomic_load(&P.hq->submitted, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-    unsigned int c = ld_relaxed(&P.dq->claimed);
-    if (c < sub) {
-      // A launch of one kind stops at the first job of the other kind; the
-      // host then relaunches with the team shape that job needs.
-      if (P.claim_kind != 0 && (ld_sys(&P.jobs[c].wide) != 0) != (P.claim_kind == 2)) return -1;
-      if (__hip_atomic_compare_exchange_strong(&P.dq->claimed, &c, c + 1, __ATOMIC_RELAXED,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-        return (int)c;
-      continue;
-    }
+    int j = -1;
+    if (P.split && team == 0 && take(&P.hq->submitted_wide, &P.dq->claimed_wide, P.ring_wide, &j)) return j;
+    if (take(&P.hq->submitted, &P.dq->claimed, P.ring, &j)) return j;
     if (++idle > P.idle_limit) return -1;
     __builtin_amdgcn_s_sleep(8);
   }
@@ -1120,7 +1135,7 @@ __device__ __forceinline__ void persistent_body(Lds &L, const Params &P) {
 
   while (!L.abort) {
     if (L.team_rank == 0 && tid == 0) {
-      const int j = claim_job(P);
+      const int j = claim_job(P, L.team);
       W.ctl->job = j;
       if (j >= 0) {
         Job *J = &P.jobs[j];
@@ -1290,6 +1305,7 @@ __global__ void init_kernel(Bar *bar, DevQueue *dq, int reset_queue) {
   if (i == 0) {
     if (reset_queue) {
       dq->claimed = 0;
+      dq->claimed_wide = 0;
       dq->completed = 0;
     }
     dq->abort = 0;
@@ -1305,6 +1321,7 @@ __global__ void init_job_kernel(Bar *bar, DevQueue *dq, Job *dst, Job job) {
   for (unsigned int k = i; k < nbar; k += gridDim.x * blockDim.x) reinterpret_cast<unsigned int *>(bar)[k] = 0;
   if (i == 0) {
     dq->claimed = 0;
+    dq->claimed_wide = 0;
     dq->completed = 0;
     dq->abort = 0;
     dq->launches = 1;

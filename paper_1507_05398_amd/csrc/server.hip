@@ -18,7 +18,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
-#include <deque>
+#include <list>
 #include <iterator>
 #include <thread>
 #include <map>
@@ -34,13 +34,19 @@ namespace gcimpl {
 constexpr unsigned int kServerSlots = 1u << 16;   // jobs over the life of one server
 constexpr unsigned int kServerIdlePolls = 50000;  // about 0.1 s of empty queue before the kernel exits
 // A job whose exhaustive work bound 2^n * capacity(n, d) reaches this is
-// "wide": it is built by a launch whose single team spans the GPU (on one
-// XCD's team it would take up to eight times longer and stretch the
-// makespan); the other jobs share the narrow teams.
+// "wide": it goes to the wide ring, which the team spanning half of the XCDs
+// serves first (on one XCD's team it would take up to eight times longer and
+// stretch the makespan); the other jobs go to the narrow ring, served by the
+// teams of the other half and, when no wide job waits, by the wide team too.
 constexpr double kWideWork = 274877906944.0;  // 2^38
+// Narrow jobs may be admitted past a wide job that waits for arena space,
+// until that wide job has waited this long; then admission stops behind it
+// until it fits.
+constexpr double kWideAdmitWaitS = 1.0;
 
 struct Ticket {
   int n, d, ord;
+  std::chrono::steady_clock::time_point submitted;
   size_t bytes = 0, offset = 0;
   bool has_space = false;   // owns `bytes` of the arena at `offset`
   int state = GC_JOB_WAITING;
@@ -52,7 +58,8 @@ struct Ticket {
 
 struct gc_server {
   std::mutex mu;
-  int teams = 8;            // narrow teams (jobs below the wide threshold)
+  int teams = 8;            // as passed to gc_server_create
+  int launch_teams = 1;     // teams of a launch: `teams`, or 1 wide + `teams` narrow (one XCD each)
   bool stopped = false;     // a bounded device-side wait expired: no further launches
   unsigned int grid = 0;
   hipStream_t stream = nullptr;
@@ -74,11 +81,13 @@ struct gc_server {
   gcimpl::Job *jobs = nullptr;
   gcimpl::HostQueue *hq_dev = nullptr;
   gcimpl::Job *jobs_dev = nullptr;
-  unsigned int published = 0;
+  unsigned int *ring = nullptr, *ring_dev = nullptr;            // narrow ring (pinned, mapped)
+  unsigned int *ring_wide = nullptr, *ring_wide_dev = nullptr;  // wide ring
+  unsigned int published = 0, published_narrow = 0, published_wide = 0;
   // host bookkeeping
   std::map<size_t, size_t> free_ranges;   // offset -> length
   std::map<uint64_t, gcimpl::Ticket> tickets;
-  std::deque<uint64_t> waiting;
+  std::list<uint64_t> waiting;
   std::set<uint64_t> inflight;            // admitted, not yet seen finished
   std::vector<uint64_t> slot_ticket;
   uint64_t next_ticket = 1;
@@ -122,14 +131,16 @@ bool kernel_running(gc_server *s) {
   return hipEventQuery(s->kernel_done) == hipErrorNotReady;
 }
 
+// Wide XCDs of a server: teams 2 and 4 split the 8 XCDs into one wide team
+// of 8 - teams XCDs and `teams` narrow teams of one XCD; teams 1 and 8 have
+// equal teams (one team spanning the GPU, or one per XCD) and one queue.
+int wide_xcds(int teams) { return teams == 2 || teams == 4 ? 8 - teams : 0; }
+
 bool is_wide(const gc_server *s, int n, int d) {
-  return s->teams > 1 && std::ldexp((double)greedy_code_capacity(n, d), n) >= kWideWork;
+  return wide_xcds(s->teams) > 0 && std::ldexp((double)greedy_code_capacity(n, d), n) >= kWideWork;
 }
 
-// Launch the persistent kernel for the next unclaimed job: one GPU-wide team
-// if that job is wide, the narrow teams otherwise.  Each launch stops at the
-// first job of the other kind.
-int launch_server_kernel(gc_server *s, bool wide) {
+int launch_server_kernel(gc_server *s) {
   Params P;
   memset(&P, 0, sizeof(P));
   P.jobs = s->jobs_dev;
@@ -137,8 +148,10 @@ int launch_server_kernel(gc_server *s, bool wide) {
   P.dq = s->dq;
   P.bar = s->bar;
   P.njobs_fixed = -1;
-  P.nteams = wide ? 1 : s->teams;
-  P.claim_kind = s->teams == 1 ? 0 : (wide ? 2 : 1);
+  P.nteams = s->launch_teams;
+  P.split = wide_xcds(s->teams);
+  P.ring = s->ring_dev;
+  P.ring_wide = s->ring_wide_dev;
   P.spin_limit = 1u << 25;
   if (const char *env = getenv("GC_SPIN_LIMIT")) P.spin_limit = (unsigned int)strtoul(env, nullptr, 0);
   P.idle_limit = kServerIdlePolls;
@@ -182,16 +195,29 @@ void fail_unfinished(gc_server *s, int code) {
 int pump(gc_server *s) {
   if (s->stopped) return GC_OK;
   bool published_any = false;
-  while (!s->waiting.empty()) {
-    const uint64_t id = s->waiting.front();
+  // Arrival order, except that a narrow job may pass a wide job that waits
+  // for arena space (for at most kWideAdmitWaitS, so wide jobs do not
+  // starve).
+  const auto now = std::chrono::steady_clock::now();
+  bool blocked_wide = false;
+  for (auto it = s->waiting.begin(); it != s->waiting.end();) {
+    const uint64_t id = *it;
     Ticket &t = s->tickets[id];
+    const bool wide = is_wide(s, t.n, t.d);
+    if (!wide && blocked_wide) break;
     size_t off = 0;
-    if (!arena_alloc(s, t.bytes, &off)) break;  // first come, first served
+    if (!arena_alloc(s, t.bytes, &off)) {
+      if (!wide) break;  // narrow jobs are admitted in order
+      const double waited = std::chrono::duration<double>(now - t.submitted).count();
+      if (waited > kWideAdmitWaitS) blocked_wide = true;
+      ++it;
+      continue;
+    }
     if (s->published >= kServerSlots) {
       arena_free(s, off, t.bytes);
       return fail(GC_ENOMEM, "server job slots exhausted (%u)", kServerSlots);
     }
-    s->waiting.pop_front();
+    it = s->waiting.erase(it);
     t.offset = off;
     t.has_space = true;
     t.slot = (int)s->published;
@@ -205,7 +231,9 @@ int pump(gc_server *s) {
     J->capacity = greedy_code_capacity(t.n, t.d);
     J->count = nullptr;
     J->host_copy = reinterpret_cast<uint32_t *>(s->mirror_dev + off);
-    J->wide = is_wide(s, t.n, t.d) ? 1 : 0;
+    J->wide = wide ? 1 : 0;
+    if (J->wide) s->ring_wide[s->published_wide++] = (unsigned int)t.slot;
+    else s->ring[s->published_narrow++] = (unsigned int)t.slot;
     gc_tuning tu;
     if (tuned_for(t.n, t.d, t.ord, &tu)) {
       J->near_depth = tu.near_depth;
@@ -220,7 +248,8 @@ int pump(gc_server *s) {
   }
   if (published_any) {
     std::atomic_thread_fence(std::memory_order_seq_cst);
-    __atomic_store_n(&s->hq->submitted, s->published, __ATOMIC_RELEASE);
+    __atomic_store_n(&s->hq->submitted_wide, s->published_wide, __ATOMIC_RELEASE);
+    __atomic_store_n(&s->hq->submitted, s->published_narrow, __ATOMIC_RELEASE);
   }
   // Relaunch if published jobs are unfinished and no kernel is running (the
   // previous one may have gone idle just before the publication, stopped at
@@ -249,8 +278,7 @@ int pump(gc_server *s) {
       fail_unfinished(s, GC_ETIMEOUT);
       return GC_OK;
     }
-    const bool wide = dq.claimed < s->published && s->jobs[dq.claimed].wide;
-    return launch_server_kernel(s, wide);
+    return launch_server_kernel(s);
   }
   return GC_OK;
 }
@@ -284,11 +312,12 @@ int gc_server_create(size_t arena_bytes, int teams, gc_server **out) {
   if (!coop || bpc < 1) return fail(GC_EDEVICE, "cooperative persistent kernel unavailable");
   gc_server *s = new gc_server();
   s->teams = teams;
+  s->launch_teams = wide_xcds(teams) ? 1 + teams : teams;
   s->grid = (unsigned int)cus;
   s->arena_bytes = round256(arena_bytes);
   const size_t off_dq = round256(sizeof(Bar));
   const size_t off_ws = off_dq + round256(sizeof(DevQueue));
-  const size_t ws_bytes = off_ws + team_workspace_bytes() * (size_t)teams;
+  const size_t ws_bytes = off_ws + team_workspace_bytes() * (size_t)s->launch_teams;
   hipError_t e = hipMalloc((void **)&s->dev, ws_bytes);
   if (e == hipSuccess) e = hipMalloc((void **)&s->arena, s->arena_bytes);
   if (e == hipSuccess) e = hipMemset(s->dev, 0, ws_bytes);
@@ -298,6 +327,13 @@ int gc_server_create(size_t arena_bytes, int teams, gc_server **out) {
     e = hipHostMalloc((void **)&s->jobs, sizeof(Job) * kServerSlots, hipHostMallocCoherent | hipHostMallocMapped);
   if (e == hipSuccess)
     e = hipHostMalloc((void **)&s->mirror, s->arena_bytes, hipHostMallocCoherent | hipHostMallocMapped);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void **)&s->ring, sizeof(unsigned int) * kServerSlots, hipHostMallocCoherent | hipHostMallocMapped);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void **)&s->ring_wide, sizeof(unsigned int) * kServerSlots,
+                      hipHostMallocCoherent | hipHostMallocMapped);
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&s->ring_dev, s->ring, 0);
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&s->ring_wide_dev, s->ring_wide, 0);
   if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&s->mirror_dev, s->mirror, 0);
   if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&s->hq_dev, s->hq, 0);
   if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&s->jobs_dev, s->jobs, 0);
@@ -330,6 +366,7 @@ int gc_server_submit(gc_server *s, int n, int d, int ordering, uint64_t *ticket)
   t.d = d;
   t.ord = ordering;
   t.bytes = round256(greedy_code_capacity(n, d) * sizeof(uint32_t));
+  t.submitted = std::chrono::steady_clock::now();
   if (t.bytes > s->arena_bytes)
     return fail(GC_ENOMEM, "job needs %zu bytes, arena holds %zu", t.bytes, s->arena_bytes);
   const uint64_t id = s->next_ticket++;
@@ -457,6 +494,8 @@ int gc_server_destroy(gc_server *s) {
   if (s->hq) (void)hipHostFree(s->hq);
   if (s->arena) (void)hipFree(s->arena);
   if (s->mirror) (void)hipHostFree(s->mirror);
+  if (s->ring) (void)hipHostFree(s->ring);
+  if (s->ring_wide) (void)hipHostFree(s->ring_wide);
   if (s->dev) (void)hipFree(s->dev);
   delete s;
   return GC_OK;

@@ -85,6 +85,8 @@ def test_batched_workload_256_instances():
 
 JOBS = [(14, 3, "lex"), (16, 5, "gray"), (12, 4, "grlex"), (15, 6, "grevlex"), (18, 3, "gray"),
         (10, 2, "lex"), (17, 8, "grlex"), (13, 7, "lex"), (20, 4, "grevlex"), (11, 3, "gray")]
+# wide jobs (2^n * capacity >= 2^38) for the servers with a wide team
+WIDE_JOBS = [(22, 3, "grlex"), (23, 4, "lex")]
 
 
 def wait_all(srv, tickets, timeout=120.0):
@@ -99,18 +101,19 @@ def wait_all(srv, tickets, timeout=120.0):
         time.sleep(0.001)
 
 
-def test_server_alone_and_in_the_mix_match_oracle():
-    expected = [ref(*j) for j in JOBS]
-    with gc.Server(arena_bytes=64 << 20, teams=8) as srv:
+@pytest.mark.parametrize("teams", [8, 2])
+def test_server_alone_and_in_the_mix_match_oracle(teams):
+    expected = [ref(*j) for j in JOBS + WIDE_JOBS]
+    with gc.Server(arena_bytes=64 << 20, teams=teams) as srv:
         # alone: one job at a time
-        for j, e in zip(JOBS, expected):
+        for j, e in zip(JOBS + WIDE_JOBS, expected):
             log(f"[gpu] server alone {j}")
             t = srv.submit(*j)
             wait_all(srv, [t])
             assert np.array_equal(srv.fetch(t), e), j
             srv.release(t)
         # in the mix: everything at once, twice over
-        tickets = [srv.submit(*j) for j in JOBS + JOBS]
+        tickets = [srv.submit(*j) for j in JOBS + WIDE_JOBS + JOBS + WIDE_JOBS]
         wait_all(srv, tickets)
         for t, e in zip(tickets, expected + expected):
             assert np.array_equal(srv.fetch(t), e)
@@ -221,8 +224,9 @@ def load_served_digests():
 def test_served_triples_match_oracle_digests():
     """Every distinct (n, d, ordering) of the served workload's stream (seed
     1507, 10,000 jobs: n in [10, 26], d in [3, 10], all four orderings)
-    through an 8-team server with a 16 MiB arena (admission binds; wide jobs
-    run GPU-wide), each result against the oracle's digest."""
+    through a server with a wide team (6 XCDs) and two narrow teams and a
+    16 MiB arena (admission binds; narrow jobs pass waiting wide ones), each
+    result against the oracle's digest."""
     import hashlib
     exp = load_served_digests()
     triples = sorted({(n, d, o) for _, n, d, o in workloads.served_jobs(seed=1507, count=10000, rate=1.0)},
@@ -231,7 +235,7 @@ def test_served_triples_match_oracle_digests():
     assert set(keys) == set(exp), "tests/golden/expected_served.txt does not match the served stream"
     log(f"[served] {len(triples)} distinct triples, {sum(t[0] > 20 for t in triples)} with n > 20")
     got, waited = {}, 0
-    with gc.Server(arena_bytes=16 << 20, teams=8) as srv:
+    with gc.Server(arena_bytes=16 << 20, teams=2) as srv:
         open_tickets = {srv.submit(n, d, o): k for (n, d, o), k in zip(triples, keys)}
         deadline = time.time() + 300
         while open_tickets and time.time() < deadline:
@@ -256,7 +260,7 @@ def test_server_wait_expiry_fails_jobs_and_drains():
     os.environ["GC_SPIN_LIMIT"] = "0"
     try:
         with gc.Server(arena_bytes=16 << 20, teams=4) as srv:
-            jobs = [(14, 3, "lex"), (13, 4, "gray"), (12, 5, "grlex")]
+            jobs = [(14, 3, "lex"), (13, 4, "gray"), (12, 5, "grlex"), (24, 4, "gray")]
             tickets = [srv.submit(*j) for j in jobs]
             srv.drain(timeout_ms=60000)
             states = [srv.poll(t)[0] for t in tickets]
