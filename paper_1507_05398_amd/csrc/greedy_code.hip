@@ -315,39 +315,34 @@ __device__ __forceinline__ void team_join(Lds &L, const Params &P) {
   __syncthreads();
 }
 
-// Team-wide barrier, two levels.  Workgroups of one XCD meet on that XCD's
-// counter; the last to arrive (the XCD leader) makes the XCD's writes visible
-// device-wide (release), meets the other leaders of the team, acquires, and
-// releases its XCD.  Every workgroup then acquires at agent scope before it
-// reads data written elsewhere.  Waits are bounded by `limit` polls.
+// Team-wide barrier, two levels of arrival.  Workgroups count themselves on
+// their XCD's counter; the last to arrive (the XCD leader) makes the XCD's
+// writes visible device-wide (release) and counts the XCD on the team
+// counter; the last XCD leader bumps the team's generation.  Every workgroup
+// waits for that generation to change and then acquires at agent scope
+// before it reads data written elsewhere.  Waits are bounded by `limit`
+// polls.
 __device__ __forceinline__ void team_barrier(Lds &L, const Params &P, unsigned int limit) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     Bar *B = P.bar;
     unsigned int *xc = &B->xcd[L.xcd][0];
-    unsigned int *xg = &B->xcd[L.xcd][1];
-    const unsigned int g = ld_relaxed(xg);
+    unsigned int *tc = &B->team[L.team][0];
+    unsigned int *tgp = &B->team[L.team][1];
+    // The generation cannot move before this workgroup has arrived.
+    const unsigned int tg = ld_relaxed(tgp);
     const unsigned int a = __hip_atomic_fetch_add(xc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (a + 1 == L.xcd_members) {
       __hip_atomic_store(xc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      unsigned int *tc = &B->team[L.team][0];
-      unsigned int *tgp = &B->team[L.team][1];
-      const unsigned int tg = ld_relaxed(tgp);
       const unsigned int b = __hip_atomic_fetch_add(tc, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       if (b + 1 == L.team_xcds) {
         __hip_atomic_store(tc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(tgp, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        wait_change(tgp, tg, P, limit);
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      __builtin_amdgcn_s_waitcnt(0);
-      __hip_atomic_fetch_add(xg, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      wait_change(xg, g, P, limit);
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
+    wait_change(tgp, tg, P, limit);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __builtin_amdgcn_s_waitcnt(0);
     L.abort = ld_relaxed(&P.dq->abort);
   }
