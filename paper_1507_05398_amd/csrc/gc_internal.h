@@ -75,7 +75,8 @@ struct Ctl {
   int job;                // job being built, -1 when the team stops
   unsigned long long stat_windows, stat_rounds, stat_surv, stat_near, stat_deep, stat_pairs;
   unsigned long long ticks[4];   // near screen, survivors+pairs, resolve, deep scan
-  unsigned int pad[24];
+  unsigned int resolved;          // generation: bumped by team rank 0 after each resolve
+  unsigned int pad[23];
 };
 
 // Barrier state: per XCD a counter, a generation and the member count (each

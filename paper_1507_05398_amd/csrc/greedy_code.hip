@@ -187,6 +187,7 @@ struct Lds {
   // window
   unsigned long long p0, m0, w, pe, lo;
   unsigned int s, s_tot, ndeep, round, tcount, truncated;
+  unsigned int gen_seen;               // resolve generation before the barrier that precedes a resolve
   int status, action, abort;
   // team
   unsigned int xcd, xcd_members, team, team_rank, team_size, team_xcds;
@@ -1023,13 +1024,29 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
         if (tid == 0) L.cnt_deep += c;
       });
     }
+    if (tid == 0) L.gen_seen = ld_relaxed(&ctl->resolved);  // cannot move before this barrier
     team_barrier(L, P, P.spin_limit);
     charge(deep_now ? 3 : 1);
 
     // ---- D / E rounds ------------------------------------------------------
     for (;;) {
-      if (L.team_rank == 0) resolve_window(L, W);
-      team_barrier(L, P, P.spin_limit);
+      // Only team rank 0 writes between the barrier before the resolve and
+      // the next phase, so the others need not meet it: rank 0 releases its
+      // writes and bumps the resolve generation, the others wait for that
+      // (bounded) and acquire.
+      if (L.team_rank == 0) {
+        resolve_window(L, W);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0)
+          __hip_atomic_fetch_add(&ctl->resolved, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else if (tid == 0) {
+        wait_change(&ctl->resolved, L.gen_seen, P, P.spin_limit);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_s_waitcnt(0);
+        L.abort = ld_relaxed(&P.dq->abort);
+      }
+      __syncthreads();
       charge(2);
       if (tid == 0) {
         L.action = ld_relaxed(&ctl->action);
@@ -1053,7 +1070,10 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
           if (tid == 0) L.cnt_deep += c;
         });
       }
-      if (tid == 0) L.round += 1;
+      if (tid == 0) {
+        L.round += 1;
+        L.gen_seen = ld_relaxed(&ctl->resolved);
+      }
       team_barrier(L, P, P.spin_limit);
       charge(3);
     }
