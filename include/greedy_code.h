@@ -92,6 +92,11 @@ typedef struct gc_tuning {
                                the old code together, newest first; smaller
                                tiles mean fewer workgroups per sweep, so a
                                candidate killed deep is dropped sooner. */
+    uint32_t valu_screen;   /* 0 = distance screens on the matrix cores (bits as
+                               signed bytes, one int8 matrix product per 32
+                               words x 32 candidates); 1 = popcounts of XORs
+                               on the vector ALU.  Self-orthogonal screens
+                               always use the vector ALU. */
 } gc_tuning;
 
 /* Capacity (in words) that always suffices for (n, d): the sphere-packing

@@ -51,7 +51,7 @@ class GcStats(ctypes.Structure):
 class GcTuning(ctypes.Structure):
     _fields_ = [("near_depth", ctypes.c_uint64), ("target_survivors", ctypes.c_uint32),
                 ("grid_blocks", ctypes.c_uint32), ("resolve_mode", ctypes.c_uint32),
-                ("deep_tile", ctypes.c_uint32)]
+                ("deep_tile", ctypes.c_uint32), ("valu_screen", ctypes.c_uint32)]
 
 
 class GcProblem(ctypes.Structure):
@@ -218,9 +218,10 @@ def greedy_code_device_noalloc(n: int, d: int, ordering, words, count, stream=No
 
 
 def greedy_code_device_ex(n: int, d: int, ordering, words, count, stream=None, near_depth=0,
-                          target_survivors=0, grid_blocks=0, resolve_mode=0, deep_tile=0) -> dict:
+                          target_survivors=0, grid_blocks=0, resolve_mode=0, deep_tile=0,
+                          valu_screen=0) -> dict:
     """As greedy_code_device, with tuning knobs; returns the work counters."""
-    tuning = GcTuning(near_depth, target_survivors, grid_blocks, resolve_mode, deep_tile)
+    tuning = GcTuning(near_depth, target_survivors, grid_blocks, resolve_mode, deep_tile, valu_screen)
     stats = GcStats()
     rc = load().greedy_code_device_ex(n, d, _ordering(ordering), ctypes.c_void_p(words.data_ptr()),
                                       words.numel(), ctypes.c_void_p(count.data_ptr()),
@@ -288,11 +289,11 @@ def greedy_code_problem(p: GcProblem, prefix_words=None, capacity: int = None) -
 
 
 def greedy_code_problem_device(p: GcProblem, words, count, stream=None, near_depth=0, target_survivors=0,
-                               grid_blocks=0, resolve_mode=0, deep_tile=0) -> dict:
+                               grid_blocks=0, resolve_mode=0, deep_tile=0, valu_screen=0) -> dict:
     """Device entry point of a problem on torch tensors: ``words`` (capacity =
     numel, holding the prefix words), ``count`` one-element int64 tensor.
     Returns the work counters."""
-    tuning = GcTuning(near_depth, target_survivors, grid_blocks, resolve_mode, deep_tile)
+    tuning = GcTuning(near_depth, target_survivors, grid_blocks, resolve_mode, deep_tile, valu_screen)
     stats = GcStats()
     rc = load().greedy_code_problem_device(ctypes.byref(p), ctypes.c_void_p(words.data_ptr()), words.numel(),
                                            ctypes.c_void_p(count.data_ptr()), _stream_ptr(stream),
@@ -349,7 +350,7 @@ def greedy_code_tune(n: int, d: int, ordering, stream=None) -> dict:
                                    ctypes.byref(ms)))
     return {"near_depth": best.near_depth, "target_survivors": best.target_survivors,
             "grid_blocks": best.grid_blocks, "resolve_mode": best.resolve_mode, "deep_tile": best.deep_tile,
-            "ms": ms.value}
+            "valu_screen": best.valu_screen, "ms": ms.value}
 
 
 def greedy_code_tune_reset() -> None:

@@ -25,6 +25,7 @@ struct Job {
   unsigned long long near_depth;  // 0: default
   unsigned int target;            // 0: default
   unsigned int deep_tile;         // candidates per deep-scan tile (0: default)
+  unsigned int valu_screen;       // 1: distance screens on the vector ALU instead of the matrix cores
   uint32_t *code;                 // device array of `capacity` words (16-byte aligned)
   unsigned long long capacity;
   unsigned long long *count;      // device counter written at completion (may be null)

@@ -157,6 +157,7 @@ struct TileLds {
   alignas(16) uint32_t seg[2][kSegMax];
   uint32_t cw[2][kTile];
   uint32_t ci[2][kTile];
+  alignas(16) uint32_t cx[kTile][8];   // matrix screens: each candidate's bits as 32 signed bytes
   unsigned long long killw[kRows];     // kill mask of each row of 64 live candidates
   unsigned int wcnt[kWaves];
   unsigned long long claim[2];         // offsets (from the newest end) of claimed segments, by parity
@@ -184,6 +185,7 @@ struct Lds {
   unsigned long long capacity, total, near_depth;
   unsigned long long p_start, m_start, classes;
   unsigned int target, deep_tile;
+  int mfma;                            // screens (other than self-orthogonal ones) on the matrix cores
   // window
   unsigned long long p0, m0, w, pe, lo;
   unsigned int s, s_tot, ndeep, round, tcount, truncated;
@@ -223,6 +225,14 @@ __device__ __forceinline__ T gload(const T *p) {
 __device__ __forceinline__ unsigned long long lanemask_lt() {
   const unsigned int l = __lane_id();
   return l ? (~0ull >> (64 - l)) : 0ull;
+}
+
+// A pointer into global memory.  Operations through it are global (not flat)
+// instructions, which count only on the vector-memory counter: an atomic in
+// flight does not hold up the waits for LDS reads.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *as_global(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
 }
 
 template <typename T>
@@ -537,6 +547,104 @@ __device__ __forceinline__ void rows_chunk(TileLds &T, int cur, int buf, unsigne
   }
 }
 
+// ---- Distance screens on the matrix cores ----------------------------------
+//
+// With every bit written as a signed byte (+1 for 0, -1 for 1), the dot
+// product of two n-bit vectors is n - 2 dist(x, c), so a candidate x is
+// closer than d to a word c exactly when dot > n - 2d.  One
+// v_mfma_i32_32x32x32_i8 takes 32 words (rows of A) against 32 candidates
+// (columns of B) over the 32 bit positions: 1024 distances.  Lane l supplies
+// row or column l % 32 and the 16 bit positions 16 (l / 32) .. + 15 as its
+// 16 bytes; each lane gets back 16 dot products of its column (32 rows over
+// lanes l and l + 32).  The candidate side zeroes the bytes of bits >= n.
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// Four bits of `nib` as four signed bytes: bit k -> byte k = 1 - 2 bit.
+__device__ __forceinline__ uint32_t signed_bytes(uint32_t nib) {
+  const uint32_t spread = (nib * 0x204081u) & 0x01010101u;  // bit k -> bit 0 of byte k
+  return spread * 0xFEu + 0x01010101u;                    // 0 -> 0x01, 1 -> 0xFF, no carries
+}
+
+// A word's bits 16 h .. 16 h + 15 as the 16 bytes of a matrix operand.
+__device__ __forceinline__ v4i word_operand(uint32_t w, unsigned int h) {
+  const uint32_t x = w >> (16 * h);
+  v4i r;
+  r.x = (int)signed_bytes(x & 15u);
+  r.y = (int)signed_bytes((x >> 4) & 15u);
+  r.z = (int)signed_bytes((x >> 8) & 15u);
+  r.w = (int)signed_bytes((x >> 12) & 15u);
+  return r;
+}
+
+__device__ __forceinline__ int max3i(int a, int b, int c) { return max(max(a, b), c); }
+
+// Largest of the 32 dot products a lane holds for its column.
+__device__ __forceinline__ int max_dot(const v16i &a, const v16i &b) {
+  int m = max3i(a[0], a[1], a[2]);
+  m = max3i(m, a[3], a[4]);
+  m = max3i(m, a[5], a[6]);
+  m = max3i(m, a[7], a[8]);
+  m = max3i(m, a[9], a[10]);
+  m = max3i(m, a[11], a[12]);
+  m = max3i(m, a[13], a[14]);
+  m = max3i(m, a[15], b[0]);
+  m = max3i(m, b[1], b[2]);
+  m = max3i(m, b[3], b[4]);
+  m = max3i(m, b[5], b[6]);
+  m = max3i(m, b[7], b[8]);
+  m = max3i(m, b[9], b[10]);
+  m = max3i(m, b[11], b[12]);
+  m = max3i(m, b[13], b[14]);
+  return max(m, b[15]);
+}
+
+// Live candidates 0 .. live-1 (columns, in groups of 32) against the slen
+// staged words of seg[buf] (rows, in pairs of 32-word blocks).  A work item
+// is one pair of word blocks against a run of column groups: the pair's
+// operands are built once in registers and serve every group of the run.
+// With fewer pairs than waves the groups are split into runs so that every
+// wave has work.  The next group's candidate operand is read from LDS while
+// the current group is compared.  Kills go into the rows' kill masks (as
+// 32-bit halves) with LDS atomics that return nothing.
+__device__ __forceinline__ void mfma_segment(TileLds &T, int cur, int buf, uint32_t id0, unsigned int live_v,
+                                             unsigned int slen_v, int thr) {
+  const unsigned int tid = threadIdx.x, lane = tid & 63, h = lane >> 5, j = lane & 31;
+  // Wave-uniform values in scalar registers.
+  const unsigned int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const unsigned int live = __builtin_amdgcn_readfirstlane(live_v);
+  const unsigned int slen = __builtin_amdgcn_readfirstlane(slen_v);
+  const unsigned int groups = (live + 31) / 32, pairs = slen / 64;
+  const unsigned int runs = pairs >= (unsigned int)kWaves ? 1u : ((unsigned int)kWaves + pairs - 1) / pairs;
+  const unsigned int run_len = (groups + runs - 1) / runs;
+  uint32_t *kill32 = reinterpret_cast<uint32_t *>(T.killw);
+  // Candidate slot (index into cx) of this lane's column in group g; g < 32,
+  // so the entry is inside ci (past `live` it is stale and only masked).
+  auto slot_of = [&](unsigned int g) { return (T.ci[cur][32 * g + j] - id0) & (unsigned int)(kTile - 1); };
+  auto operand = [&](uint32_t slot) { return *reinterpret_cast<const v4i *>(&T.cx[slot][4 * h]); };
+  for (unsigned int item = wave; item < pairs * runs; item += kWaves) {
+    const unsigned int run = item / pairs, pr = item % pairs;
+    const unsigned int g0 = run * run_len, g1 = umin(groups, g0 + run_len);
+    if (g0 >= g1) continue;
+    const v4i a0 = word_operand(T.seg[buf][64 * pr + j], h);
+    const v4i a1 = word_operand(T.seg[buf][64 * pr + 32 + j], h);
+    v4i b = operand(slot_of(g0));
+    uint32_t next_slot = slot_of(g0 + 1 < g1 ? g0 + 1 : g0);
+    for (unsigned int g = g0; g < g1; ++g) {
+      const v4i bn = operand(next_slot);
+      next_slot = slot_of(g + 2 < g1 ? g + 2 : g);
+      const v16i d0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b, (v16i){0}, 0, 0, 0);
+      const v16i d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b, (v16i){0}, 0, 0, 0);
+      const unsigned long long k = __builtin_amdgcn_ballot_w64(max_dot(d0, d1) > thr);
+      const unsigned int rest = live - 32 * g;  // live columns of this group (the last may be ragged)
+      const uint32_t k32 = ((uint32_t)k | (uint32_t)(k >> 32)) & (rest >= 32 ? 0xffffffffu : (1u << rest) - 1u);
+      if (k32 && lane == 0) __hip_atomic_fetch_or(&kill32[g], k32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      b = bn;
+    }
+  }
+}
+
 // Segment length (words, a multiple of 64) staged for `live` candidates: the
 // fewer live candidates, the longer the segment, so that the work per segment
 // stays near `blocks` (row group of up to 4 rows) x (64 words) blocks: 16 for
@@ -585,7 +693,7 @@ __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &
   const unsigned long long share = (len / (2ull * members) + 63) & ~63ull;
   const unsigned int cap = share < 64 ? 64u : (share > (unsigned long long)kSegMax ? (unsigned)kSegMax : (unsigned)share);
   auto claim = [&](unsigned int l) {
-    return __hip_atomic_fetch_add(cursor, (unsigned long long)l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_fetch_add(as_global(cursor), (unsigned long long)l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   };
   // First claim: a short segment, so that the tile's first sweep is narrow.
   // It is in flight while the candidates are listed (all of them are live:
@@ -596,12 +704,26 @@ __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &
   if (tid == 0) first = claim(slen);
   bool keep = false;
   uint32_t word = 0, id = 0;
+  const bool mx = !SO && L.mfma;
   if (tid < (int)nc) {
     id = id0 + tid;
     word = src.word(id);
     T.cw[0][tid] = word;
     T.ci[0][tid] = id;
+    if (mx) {  // the candidate as 32 signed bytes, zero past bit n - 1 (its slot is tid)
+      uint32_t e[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int valid = L.n - 4 * q;  // bytes of this dword below bit n
+        const uint32_t keep = valid >= 4 ? 0xffffffffu : (valid <= 0 ? 0u : 0xffffffffu >> (32 - 8 * valid));
+        e[q] = signed_bytes((word >> (4 * q)) & 15u) & keep;
+      }
+      uint4 *dst = reinterpret_cast<uint4 *>(T.cx[tid]);
+      dst[0] = make_uint4(e[0], e[1], e[2], e[3]);
+      dst[1] = make_uint4(e[4], e[5], e[6], e[7]);
+    }
   }
+  const int thr = L.n - 2 * (int)d;  // matrix screens: a dot product above this is a clash
   int cur = 0, buf = 0;
   unsigned long long checks = 0;
   // The segment goes from global memory straight into LDS buffer `to` (the
@@ -646,7 +768,8 @@ __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &
     const bool more = next_off < len;
     if (more) fetch(next_off, next_len, buf ^ 1);  // in flight during the compute
     uint32_t seen = 0;
-    if (tid < dwords) seen = ld_relaxed(&dead[tid]);  // kills published by the other members
+    if (tid < dwords)  // kills published by the other members
+      seen = __hip_atomic_load(as_global(&dead[tid]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // Rows go to 1, 2 or 4 groups of balanced sizes (they differ by at most
     // one; 9..12 rows make 4 groups of 2-3 rather than 3 groups of 4, so that
     // the block count of a segment, groups x chunks, stays a multiple of the
@@ -657,24 +780,29 @@ __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &
     // needs a third accumulator per row).
     const unsigned int groups = SO ? (rows > 8 ? 8u : (rows > 4 ? 4u : (rows > 2 ? 2u : 1u)))
                                    : (rows > 8 ? 4u : (rows > 4 ? 2u : 1u));
-    // A wave's issue priority drops with every block it completes, so the
-    // waves of a SIMD progress together and the SIMD still has several waves
-    // to interleave when the segment's blocks run out.
-    __builtin_amdgcn_s_setprio(3);
-    unsigned int done = 0;
-    for (unsigned int blk = wave; blk < groups * chunks; blk += kWaves, ++done) {
-      const unsigned int g = blk / chunks, chunk = blk % chunks;
-      const unsigned int row0 = g * rows / groups, rg = (g + 1) * rows / groups - row0;
-      if (!SO && rg == 4) rows_chunk<4, SO>(T, cur, buf, row0, chunk, live, d);
-      else if (!SO && rg == 3) rows_chunk<3, SO>(T, cur, buf, row0, chunk, live, d);
-      else if (rg == 2) rows_chunk<2, SO>(T, cur, buf, row0, chunk, live, d);
-      else rows_chunk<1, SO>(T, cur, buf, row0, chunk, live, d);
-      if (done == 0) __builtin_amdgcn_s_setprio(2);
-      else if (done == 1) __builtin_amdgcn_s_setprio(1);
-      else __builtin_amdgcn_s_setprio(0);
+    if (mx) {
+      mfma_segment(T, cur, buf, id0, live, slen, thr);
+      checks += 32ull * ((live + 31) / 32) * slen;
+    } else {
+      // A wave's issue priority drops with every block it completes, so the
+      // waves of a SIMD progress together and the SIMD still has several waves
+      // to interleave when the segment's blocks run out.
+      __builtin_amdgcn_s_setprio(3);
+      unsigned int done = 0;
+      for (unsigned int blk = wave; blk < groups * chunks; blk += kWaves, ++done) {
+        const unsigned int g = blk / chunks, chunk = blk % chunks;
+        const unsigned int row0 = g * rows / groups, rg = (g + 1) * rows / groups - row0;
+        if (!SO && rg == 4) rows_chunk<4, SO>(T, cur, buf, row0, chunk, live, d);
+        else if (!SO && rg == 3) rows_chunk<3, SO>(T, cur, buf, row0, chunk, live, d);
+        else if (rg == 2) rows_chunk<2, SO>(T, cur, buf, row0, chunk, live, d);
+        else rows_chunk<1, SO>(T, cur, buf, row0, chunk, live, d);
+        if (done == 0) __builtin_amdgcn_s_setprio(2);
+        else if (done == 1) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
+      }
+      __builtin_amdgcn_s_setprio(0);
+      checks += 64ull * rows * slen;
     }
-    __builtin_amdgcn_s_setprio(0);
-    checks += 64ull * rows * slen;
     if (tid < 32) T.dseen[tid] = seen;
     __syncthreads();
     // Claim the segment after the next one; the atomic completes during the
@@ -695,7 +823,8 @@ __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &
     live = tile_compact(T, cur ^ 1, keep, word, id, [&] {
       if (tid < dwords) {  // one atomic per dead-bit word
         const uint32_t mine = T.dloc[tid];
-        if (mine & ~T.dseen[tid]) __hip_atomic_fetch_or(&dead[tid], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (mine & ~T.dseen[tid])
+          __hip_atomic_fetch_or(as_global(&dead[tid]), mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       if (tid < kRows) T.killw[tid] = 0;
       if (tid == 0) T.claim[1] = after_off;
@@ -1185,6 +1314,7 @@ __device__ __forceinline__ void persistent_body(Lds &L, const Params &P) {
       L.capacity = ld_sys(&J->capacity);
       const unsigned int dt = ld_sys(&J->deep_tile);
       L.deep_tile = dt ? dt : (unsigned int)kTile;
+      L.mfma = ld_sys(&J->valu_screen) == 0;
       const int wclass = ld_sys(&J->wclass);
       L.walk.n = L.n;
       L.walk.ord = L.ord;
@@ -1636,6 +1766,7 @@ void fill_job(Job *J, int n, int d, int ordering, uint32_t *words, uint64_t capa
     J->target = tuning->target_survivors;
     J->mode = (int)tuning->resolve_mode;
     J->deep_tile = tuning->deep_tile;
+    J->valu_screen = tuning->valu_screen;
   }
 }
 
@@ -1791,6 +1922,7 @@ void fill_job_problem(Job *J, const gc_problem &p, uint32_t *words, uint64_t cap
     J->target = tuning->target_survivors;
     J->mode = (int)tuning->resolve_mode;
     J->deep_tile = tuning->deep_tile;
+    J->valu_screen = tuning->valu_screen;
   }
 }
 
@@ -1873,6 +2005,7 @@ int greedy_code_problem_device(const gc_problem *p, uint32_t *d_words, uint64_t 
   if (tuning && tuning->deep_tile != 0 && tuning->deep_tile != 256 && tuning->deep_tile != 512 &&
       tuning->deep_tile != 1024)
     return fail(GC_EINVAL, "deep_tile %u must be 0, 256, 512 or 1024", tuning->deep_tile);
+  if (tuning && tuning->valu_screen > 1) return fail(GC_EINVAL, "valu_screen %u must be 0 or 1", tuning->valu_screen);
   if (stats) memset(stats, 0, sizeof(*stats));
   hipStream_t stream = (hipStream_t)hip_stream;
   const uint64_t stop = p->stop ? p->stop : positions_of(*p);

@@ -240,6 +240,7 @@ int pump(gc_server *s) {
       J->target = tu.target_survivors;
       J->mode = (int)tu.resolve_mode;
       J->deep_tile = tu.deep_tile;
+      J->valu_screen = tu.valu_screen;
     }
     s->slot_ticket[t.slot] = id;
     s->inflight.insert(id);

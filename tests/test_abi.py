@@ -223,3 +223,11 @@ def test_tuning_deep_tile_is_validated():
     rc = lib.greedy_code_device_ex(8, 3, 0, ctypes.c_void_p(64), 16, ctypes.c_void_p(64), None,
                                    ctypes.byref(t), None)
     assert rc == gc.GC_EINVAL and "deep_tile" in gc.gc_last_error()
+
+
+def test_tuning_valu_screen_is_validated():
+    lib = gc.load()
+    t = gc._native.GcTuning(0, 0, 0, 0, 0, 2)
+    rc = lib.greedy_code_device_ex(8, 3, 0, ctypes.c_void_p(64), 16, ctypes.c_void_p(64), None,
+                                   ctypes.byref(t), None)
+    assert rc == gc.GC_EINVAL and "valu_screen" in gc.gc_last_error()

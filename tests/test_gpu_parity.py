@@ -99,9 +99,12 @@ def test_host_entry_point():
                                     dict(near_depth=300, resolve_mode=2),
                                     dict(grid_blocks=13, near_depth=1, resolve_mode=2),
                                     dict(near_depth=100, deep_tile=256),
-                                    dict(near_depth=700, deep_tile=512, resolve_mode=1)],
+                                    dict(near_depth=700, deep_tile=512, resolve_mode=1),
+                                    dict(valu_screen=1),
+                                    dict(valu_screen=1, near_depth=100, deep_tile=256, resolve_mode=1)],
                          ids=["near1", "near64_t16", "nearall_t1024", "grid1", "grid7",
-                              "tentative", "deepall", "grid13_deepall", "tile256", "tile512_tentative"])
+                              "tentative", "deepall", "grid13_deepall", "tile256", "tile512_tentative",
+                              "valu", "valu_tile256_tentative"])
 def test_tuning_does_not_change_the_code(o, tuning):
     for n, d in [(16, 3), (17, 4), (16, 5), (18, 6)]:
         words, _ = gpu_code(n, d, o, **tuning)
@@ -174,5 +177,17 @@ def test_workload_instances_large(key):
     t = time.time()
     words, stats = gpu_code(int(n), int(d), o)
     log(f"[gpu] {key}: |C|={len(words)} {time.time() - t:.2f}s")
+    assert len(words) == m
+    assert digest(words) == dig
+
+
+@pytest.mark.parametrize("key", ["24_3_lex", "24_4_grlex", "24_5_gray", "24_6_grevlex", "26_3_gray"])
+def test_workload_instances_on_the_vector_alu_screen(key):
+    """The vector-ALU popcount screen (tuning valu_screen=1) builds the same
+    codes as the default matrix-core screen on full-size instances."""
+    n, d, o = key.split("_")
+    m, dig, _, _ = EXPECTED[key]
+    words, _ = gpu_code(int(n), int(d), o, valu_screen=1)
+    log(f"[gpu] {key} vector ALU: |C|={len(words)}")
     assert len(words) == m
     assert digest(words) == dig
