@@ -157,7 +157,7 @@ struct TileLds {
   alignas(16) uint32_t seg[2][kSegMax];
   uint32_t cw[2][kTile];
   uint32_t ci[2][kTile];
-  alignas(16) uint32_t cx[kTile][8];   // matrix screens: each candidate's bits as 32 signed bytes
+  alignas(16) uint32_t cx[2][kTile][8];  // matrix screens: candidate bits as 32 signed bytes, by cw order
   unsigned long long killw[kRows];     // kill mask of each row of 64 live candidates
   unsigned int wcnt[kWaves];
   unsigned long long claim[2];         // offsets (from the newest end) of claimed segments, by parity
@@ -173,6 +173,7 @@ struct ResolveLds {
 };
 
 struct Lds {
+  uint2 lut8[256];                     // byte -> its 8 bits as signed bytes (matrix screens)
   uint32_t s1w[kSMax];                 // window survivors, in position order
   uint32_t s1off[kSMax];               // their offsets from the window start
   uint8_t st[kSMax];                   // deep status of each survivor (resolve only)
@@ -467,11 +468,12 @@ struct Source {
 };
 
 // Workgroup compaction: thread t offers entry t (keep, word, id); kept
-// entries go densely and in order to buffer dst.  Returns the count.
-// `between` runs after the first barrier (everything written to LDS before
-// the call is visible to it).
-template <typename F>
-__device__ unsigned int tile_compact(TileLds &T, int dst, bool keep, uint32_t word, uint32_t id, F &&between) {
+// entries go densely and in order to buffer dst, and put(new position) runs
+// for each of them.  Returns the count.  `between` runs after the first
+// barrier (everything written to LDS before the call is visible to it).
+template <typename F, typename G>
+__device__ unsigned int tile_compact(TileLds &T, int dst, bool keep, uint32_t word, uint32_t id, F &&between,
+                                     G &&put) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const unsigned long long m = ballot(keep);
   if (lane == 0) T.wcnt[wave] = (unsigned int)__builtin_popcountll(m);
@@ -487,13 +489,14 @@ __device__ unsigned int tile_compact(TileLds &T, int dst, bool keep, uint32_t wo
     const unsigned int pos = base + (unsigned int)__builtin_popcountll(m & lanemask_lt());
     T.cw[dst][pos] = word;
     T.ci[dst][pos] = id;
+    put(pos);
   }
   __syncthreads();
   return total;
 }
 
 __device__ __forceinline__ unsigned int tile_compact(TileLds &T, int dst, bool keep, uint32_t word, uint32_t id) {
-  return tile_compact(T, dst, keep, word, id, [] {});
+  return tile_compact(T, dst, keep, word, id, [] {}, [](unsigned int) {});
 }
 
 // RG rows of 64 live candidates (rows row0 .. row0+RG-1) against the 64
@@ -567,14 +570,15 @@ __device__ __forceinline__ uint32_t signed_bytes(uint32_t nib) {
   return spread * 0xFEu + 0x01010101u;                    // 0 -> 0x01, 1 -> 0xFF, no carries
 }
 
-// A word's bits 16 h .. 16 h + 15 as the 16 bytes of a matrix operand.
-__device__ __forceinline__ v4i word_operand(uint32_t w, unsigned int h) {
-  const uint32_t x = w >> (16 * h);
+// A word's bits 16 h .. 16 h + 15 as the 16 bytes of a matrix operand, two
+// bytes of the word looked up in the table of signed-byte expansions.
+__device__ __forceinline__ v4i word_operand(const uint2 *lut8, uint32_t w, unsigned int h) {
+  const uint2 lo = lut8[(w >> (16 * h)) & 255u], hi = lut8[(w >> (16 * h + 8)) & 255u];
   v4i r;
-  r.x = (int)signed_bytes(x & 15u);
-  r.y = (int)signed_bytes((x >> 4) & 15u);
-  r.z = (int)signed_bytes((x >> 8) & 15u);
-  r.w = (int)signed_bytes((x >> 12) & 15u);
+  r.x = (int)lo.x;
+  r.y = (int)lo.y;
+  r.z = (int)hi.x;
+  r.w = (int)hi.y;
   return r;
 }
 
@@ -600,47 +604,58 @@ __device__ __forceinline__ int max_dot(const v16i &a, const v16i &b) {
   return max(m, b[15]);
 }
 
-// Live candidates 0 .. live-1 (columns, in groups of 32) against the slen
-// staged words of seg[buf] (rows, in pairs of 32-word blocks).  A work item
-// is one pair of word blocks against a run of column groups: the pair's
-// operands are built once in registers and serve every group of the run.
-// With fewer pairs than waves the groups are split into runs so that every
-// wave has work.  The next group's candidate operand is read from LDS while
-// the current group is compared.  Kills go into the rows' kill masks (as
-// 32-bit halves) with LDS atomics that return nothing.
-__device__ __forceinline__ void mfma_segment(TileLds &T, int cur, int buf, uint32_t id0, unsigned int live_v,
+// Live candidates 0 .. live-1 (columns, in groups of 32; their operands in
+// cx[cur], in the order of cw[cur]) against the slen staged words of
+// seg[buf] (rows, in pairs of 32-word blocks).  The segment's (word pair,
+// column group) units, pair-major, are cut into one contiguous range per
+// wave (they differ by at most one unit, two products); a wave builds a
+// pair's operands in registers once and runs them against its groups of that
+// pair.  The next group's candidate operand is read from LDS while the
+// current group is compared.  Kills go into the rows' kill masks (as 32-bit
+// halves) with LDS atomics that return nothing.
+__device__ __forceinline__ void mfma_segment(TileLds &T, const uint2 *lut8, int cur, int buf, unsigned int live_v,
                                              unsigned int slen_v, int thr) {
   const unsigned int tid = threadIdx.x, lane = tid & 63, h = lane >> 5, j = lane & 31;
   // Wave-uniform values in scalar registers.
   const unsigned int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const unsigned int live = __builtin_amdgcn_readfirstlane(live_v);
   const unsigned int slen = __builtin_amdgcn_readfirstlane(slen_v);
-  const unsigned int groups = (live + 31) / 32, pairs = slen / 64;
-  const unsigned int runs = pairs >= (unsigned int)kWaves ? 1u : ((unsigned int)kWaves + pairs - 1) / pairs;
-  const unsigned int run_len = (groups + runs - 1) / runs;
+  const unsigned int groups = (live + 31) / 32, units = slen / 64 * groups;
+  const unsigned int u_end = (wave + 1) * units / kWaves;
   uint32_t *kill32 = reinterpret_cast<uint32_t *>(T.killw);
-  // Candidate slot (index into cx) of this lane's column in group g; g < 32,
-  // so the entry is inside ci (past `live` it is stale and only masked).
-  auto slot_of = [&](unsigned int g) { return (T.ci[cur][32 * g + j] - id0) & (unsigned int)(kTile - 1); };
-  auto operand = [&](uint32_t slot) { return *reinterpret_cast<const v4i *>(&T.cx[slot][4 * h]); };
-  for (unsigned int item = wave; item < pairs * runs; item += kWaves) {
-    const unsigned int run = item / pairs, pr = item % pairs;
-    const unsigned int g0 = run * run_len, g1 = umin(groups, g0 + run_len);
-    if (g0 >= g1) continue;
-    const v4i a0 = word_operand(T.seg[buf][64 * pr + j], h);
-    const v4i a1 = word_operand(T.seg[buf][64 * pr + 32 + j], h);
-    v4i b = operand(slot_of(g0));
-    uint32_t next_slot = slot_of(g0 + 1 < g1 ? g0 + 1 : g0);
-    for (unsigned int g = g0; g < g1; ++g) {
-      const v4i bn = operand(next_slot);
-      next_slot = slot_of(g + 2 < g1 ? g + 2 : g);
-      const v16i d0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b, (v16i){0}, 0, 0, 0);
-      const v16i d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b, (v16i){0}, 0, 0, 0);
-      const unsigned long long k = __builtin_amdgcn_ballot_w64(max_dot(d0, d1) > thr);
-      const unsigned int rest = live - 32 * g;  // live columns of this group (the last may be ragged)
-      const uint32_t k32 = ((uint32_t)k | (uint32_t)(k >> 32)) & (rest >= 32 ? 0xffffffffu : (1u << rest) - 1u);
-      if (k32 && lane == 0) __hip_atomic_fetch_or(&kill32[g], k32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      b = bn;
+  // This lane's 16 bytes of group g's operand (columns past `live` hold stale
+  // operands; their results are masked): 32 candidates x 32 bytes per group.
+  const v4i *ops = reinterpret_cast<const v4i *>(&T.cx[cur][j][4 * h]);
+  auto group = [&](unsigned int g, const v16i &d0, const v16i &d1) {
+    const unsigned long long k = __builtin_amdgcn_ballot_w64(max_dot(d0, d1) > thr);
+    const unsigned int rest = live - 32 * g;  // live columns of this group (the last may be ragged)
+    const uint32_t k32 = ((uint32_t)k | (uint32_t)(k >> 32)) & (rest >= 32 ? 0xffffffffu : (1u << rest) - 1u);
+    if (k32 && lane == 0) __hip_atomic_fetch_or(&kill32[g], k32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
+  for (unsigned int u = wave * units / kWaves; u < u_end;) {
+    const unsigned int pr = u / groups, g0 = u % groups, g1 = umin(groups, g0 + (u_end - u));
+    u += g1 - g0;
+    const v4i a0 = word_operand(lut8, T.seg[buf][64 * pr + j], h);
+    const v4i a1 = word_operand(lut8, T.seg[buf][64 * pr + 32 + j], h);
+    // Two groups per step, their operands in alternating registers; the
+    // read of the next step's first operand overlaps the second group.
+    const v4i *p = ops + 64 * g0;
+    v4i b0 = p[0];
+    unsigned int g = g0;
+    for (; g + 1 < g1; g += 2, p += 128) {
+      const v4i b1 = p[64];
+      const v16i d0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, (v16i){0}, 0, 0, 0);
+      const v16i d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b0, (v16i){0}, 0, 0, 0);
+      group(g, d0, d1);
+      b0 = p[g + 2 < g1 ? 128 : 64];
+      const v16i e0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b1, (v16i){0}, 0, 0, 0);
+      const v16i e1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, (v16i){0}, 0, 0, 0);
+      group(g + 1, e0, e1);
+    }
+    if (g < g1) {
+      const v16i d0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, (v16i){0}, 0, 0, 0);
+      const v16i d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b0, (v16i){0}, 0, 0, 0);
+      group(g, d0, d1);
     }
   }
 }
@@ -710,7 +725,7 @@ __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &
     word = src.word(id);
     T.cw[0][tid] = word;
     T.ci[0][tid] = id;
-    if (mx) {  // the candidate as 32 signed bytes, zero past bit n - 1 (its slot is tid)
+    if (mx) {  // the candidate as 32 signed bytes, zero past bit n - 1
       uint32_t e[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -718,7 +733,7 @@ __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &
         const uint32_t keep = valid >= 4 ? 0xffffffffu : (valid <= 0 ? 0u : 0xffffffffu >> (32 - 8 * valid));
         e[q] = signed_bytes((word >> (4 * q)) & 15u) & keep;
       }
-      uint4 *dst = reinterpret_cast<uint4 *>(T.cx[tid]);
+      uint4 *dst = reinterpret_cast<uint4 *>(T.cx[0][tid]);
       dst[0] = make_uint4(e[0], e[1], e[2], e[3]);
       dst[1] = make_uint4(e[4], e[5], e[6], e[7]);
     }
@@ -781,7 +796,7 @@ __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &
     const unsigned int groups = SO ? (rows > 8 ? 8u : (rows > 4 ? 4u : (rows > 2 ? 2u : 1u)))
                                    : (rows > 8 ? 4u : (rows > 4 ? 2u : 1u));
     if (mx) {
-      mfma_segment(T, cur, buf, id0, live, slen, thr);
+      mfma_segment(T, L.lut8, cur, buf, live, slen, thr);
       checks += 32ull * ((live + 31) / 32) * slen;
     } else {
       // A wave's issue priority drops with every block it completes, so the
@@ -818,6 +833,11 @@ __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &
       if (killed) atomicOr(&T.dloc[(id - id0) >> 5], 1u << (id & 31));
     }
     keep = tid < (int)live && !killed && !((T.dseen[(id - id0) >> 5] >> (id & 31)) & 1);
+    uint4 op0, op1;  // matrix screens: the candidate's operand moves with it
+    if (mx && keep) {
+      op0 = reinterpret_cast<const uint4 *>(T.cx[cur][tid])[0];
+      op1 = reinterpret_cast<const uint4 *>(T.cx[cur][tid])[1];
+    }
     // The kills are published after the compaction's first barrier, which
     // also completes the gathering in dloc and the reads of the kill masks.
     live = tile_compact(T, cur ^ 1, keep, word, id, [&] {
@@ -829,6 +849,11 @@ __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &
       if (tid < kRows) T.killw[tid] = 0;
       if (tid == 0) T.claim[1] = after_off;
       fetched();  // the next segment is in LDS for every wave after the barrier
+    }, [&](unsigned int pos) {
+      if (mx) {
+        reinterpret_cast<uint4 *>(T.cx[cur ^ 1][pos])[0] = op0;
+        reinterpret_cast<uint4 *>(T.cx[cur ^ 1][pos])[1] = op1;
+      }
     });
     if (!more) break;
     cur ^= 1;
@@ -1271,6 +1296,7 @@ __device__ int claim_job(const Params &P, unsigned int team) {
 template <bool SO>
 __device__ __forceinline__ void persistent_body(Lds &L, const Params &P) {
   const int tid = threadIdx.x;
+  if (tid < 256) L.lut8[tid] = make_uint2(signed_bytes((uint32_t)tid & 15u), signed_bytes((uint32_t)tid >> 4));
   team_join(L, P);
   char *base = P.team_ws + (unsigned long long)L.team * P.team_ws_stride;
   const TeamWs W = team_ws(base);
