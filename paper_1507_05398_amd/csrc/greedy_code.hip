@@ -80,17 +80,17 @@ constexpr unsigned int kDefaultTargetLinear = 1000;  // lex and Gray (window cut
 constexpr unsigned long long kDefaultNear = 16384;
 constexpr unsigned long long kDefaultNearGray = 8192;
 // Work per segment after the first, in (group of 4 rows) x (64 words) blocks
-// (measured on the n=24..28 screens): short segments for a near screen over
+// (measured on the n=24..28 screens, matrix-core screen): short segments for a near screen over
 // the newest words, where candidates die early and kills should spread
 // fast; longer ones for the deep scan and for a near screen over the whole
 // code, where most candidates survive long ranges.
 constexpr unsigned int kNearBlocks = 16;
-constexpr unsigned int kDeepBlocks = 32;
+constexpr unsigned int kDeepBlocks = 64;
 // Deep scans take segments of kFarBlocks blocks once the sweep is kFarAt
 // words below the newest end of its range: most survivors that a deep scan
 // kills die near that end, so deeper segments lose little to the lag of the
 // kills and halve the per-segment merges.
-constexpr unsigned int kFarBlocks = 64;
+constexpr unsigned int kFarBlocks = 128;
 constexpr unsigned long long kFarAt = 1ull << 19;
 constexpr unsigned int kDefaultSpin = 1u << 25;
 
@@ -632,7 +632,9 @@ __device__ __forceinline__ void mfma_segment(TileLds &T, const uint2 *lut8, int 
     const uint32_t k32 = ((uint32_t)k | (uint32_t)(k >> 32)) & (rest >= 32 ? 0xffffffffu : (1u << rest) - 1u);
     if (k32 && lane == 0) __hip_atomic_fetch_or(&kill32[g], k32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   };
-  for (unsigned int u = wave * units / kWaves; u < u_end;) {
+  const unsigned int u_begin = wave * units / kWaves, share = u_end - u_begin;
+  __builtin_amdgcn_s_setprio(3);
+  for (unsigned int u = u_begin; u < u_end;) {
     const unsigned int pr = u / groups, g0 = u % groups, g1 = umin(groups, g0 + (u_end - u));
     u += g1 - g0;
     const v4i a0 = word_operand(lut8, T.seg[buf][64 * pr + j], h);
@@ -651,6 +653,12 @@ __device__ __forceinline__ void mfma_segment(TileLds &T, const uint2 *lut8, int 
       const v16i e0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b1, (v16i){0}, 0, 0, 0);
       const v16i e1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, (v16i){0}, 0, 0, 0);
       group(g + 1, e0, e1);
+      // Issue priority falls as the wave's share is done, so that the waves
+      // of a SIMD finish together.
+      const unsigned int done4 = 4 * (u - (g1 - g - 2) - u_begin);
+      if (done4 >= 3 * share) __builtin_amdgcn_s_setprio(0);
+      else if (done4 >= 2 * share) __builtin_amdgcn_s_setprio(1);
+      else if (done4 >= share) __builtin_amdgcn_s_setprio(2);
     }
     if (g < g1) {
       const v16i d0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, (v16i){0}, 0, 0, 0);
@@ -658,6 +666,7 @@ __device__ __forceinline__ void mfma_segment(TileLds &T, const uint2 *lut8, int 
       group(g, d0, d1);
     }
   }
+  __builtin_amdgcn_s_setprio(0);
 }
 
 // Segment length (words, a multiple of 64) staged for `live` candidates: the
