@@ -44,11 +44,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 ORDS = ["lex", "gray", "grlex", "grevlex"]
-# MI355X: 256 CUs x 64 int32 lanes per clock x 2.4 GHz, and one distance check
-# costs 2.5 VALU lane-ops (v_xor_b32 + v_bcnt_u32_b32 + half a v_min3_u32).
+# MI355X: 256 CUs x 64 int32 lanes per clock x 2.4 GHz.  The vector-ALU screen
+# costs 2.5 lane-ops per distance check (v_xor_b32 + v_bcnt_u32_b32 + half a
+# v_min3_u32): PEAK_GCHECKS is that screen's ceiling.
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 OPS_PER_CHECK = 2.5
 PEAK_GCHECKS = VALU_LANE_OPS / OPS_PER_CHECK / 1e9
+# The default screen runs on the matrix cores: bits as signed bytes, a check is
+# an int8 dot product.  Its roofline is MI355X's dense int8 MFMA peak, with 2n
+# int8 operations (n multiply-adds) per check of n-bit words.  Two check-rate
+# ceilings bound it: the instruction's 32-byte rows (64 operations per check
+# whatever n is) and the max-fold of the products on the vector ALU (half a
+# lane-op per check: v_max3_i32 folds two products).
+INT8_PEAK_TOPS = 5000.0
+MFMA_CHECKS_PEAK_G = INT8_PEAK_TOPS * 1e12 / 64 / 1e9
+FOLD_CHECKS_PEAK_G = VALU_LANE_OPS / 0.5 / 1e9
 
 
 def progress(msg):
@@ -198,11 +208,13 @@ class LaunchLog:
 
     def __init__(self):
         self.ms, self.w_ee, self.executed, self.launches = 0.0, 0, 0, 0
+        self.ops = 0  # int8 operations: 2n per algorithmic check
         self.per_key = {}
 
     def add(self, key, stats, w_ee):
         self.ms += stats["kernel_ms"]
         self.w_ee += w_ee
+        self.ops += 2 * int(key.split("_")[0]) * w_ee
         self.executed += stats["checks_near"] + stats["checks_deep"] + stats["checks_pairs"]
         self.launches += 1
         self.per_key.setdefault(key, []).append(stats["kernel_ms"])
@@ -212,6 +224,9 @@ class LaunchLog:
 
     def gchecks(self):
         return self.w_ee / (self.ms / 1e3) / 1e9 if self.ms else 0.0
+
+    def tops(self):
+        return self.ops / (self.ms / 1e3) / 1e12 if self.ms else 0.0
 
 
 def bench_sweep(gc, torch, insts, expected, steps, warmup):
@@ -494,6 +509,10 @@ def main():
             v = gc.probe_block_loop(wgs_per_cu=k, iters=4096) / 1e9
             out[f"block_loop_{k}wg_per_cu_gchecks_per_s"] = round(v, 1)
             out[f"block_loop_{k}wg_per_cu_frac_of_peak"] = round(v / PEAK_GCHECKS, 4)
+        v = gc.probe_matrix_loop(iters=2048) / 1e9
+        out["matrix_loop_gchecks_per_s"] = round(v, 1)
+        out["matrix_loop_frac_of_mfma_checks_ceiling"] = round(v / MFMA_CHECKS_PEAK_G, 4)
+        out["matrix_loop_tops_at_n28"] = round(v * 56 / 1e3, 1)
         out["team_barrier_us"] = round(gc.probe_barrier(iters=20000), 3)
         print(json.dumps(out), flush=True)
         return
@@ -542,12 +561,17 @@ def main():
         batched = bench_batched(gc, torch, max(args.steps, 3), args.warmup)
         progress("batched done")
     line["roofline"] = {
-        "bound": "alu",
+        "bound": "mfma",
         "kernel": "greedy_code_kernel",
-        "achieved": round(sweep.gchecks(), 3),
-        "peak": round(PEAK_GCHECKS, 1),
-        "unit": "Gchecks/s",
-        "frac": round(sweep.gchecks() / PEAK_GCHECKS, 5),
+        "achieved": round(sweep.tops(), 3),
+        "peak": INT8_PEAK_TOPS,
+        "unit": "TOP/s (int8: 2n operations per check of n-bit words)",
+        "frac": round(sweep.tops() / INT8_PEAK_TOPS, 5),
+        "achieved_gchecks_per_s": round(sweep.gchecks(), 3),
+        "checks_ceiling_mfma_gchecks_per_s": round(MFMA_CHECKS_PEAK_G, 1),
+        "checks_ceiling_fold_gchecks_per_s": round(FOLD_CHECKS_PEAK_G, 1),
+        "frac_of_checks_ceiling": round(sweep.gchecks() / min(MFMA_CHECKS_PEAK_G, FOLD_CHECKS_PEAK_G), 5),
+        "valu_screen_peak_gchecks_per_s": round(PEAK_GCHECKS, 1),
         "traffic": measured_traffic(),
         "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE, copy-calibrated)",
         "launches": sweep.launches,

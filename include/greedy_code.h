@@ -338,10 +338,15 @@ int gc_server_destroy(gc_server *srv);
  * v_bcnt_u32_b32 and v_min3_u32, 2.5 VALU ops per distance check) in
  * wgs_per_cu (1 or 2) workgroups of 1024 threads per compute unit for
  * `iters` calls per wave, and returns the distance checks per second.
- * gc_probe_barrier times `iters` team-wide barriers of the persistent kernel
- * (one team spanning the GPU) and returns microseconds per barrier.  Both run
- * on the null stream and synchronize. */
+ * gc_probe_matrix_loop runs the matrix-core screen's segment loop alone (one
+ * workgroup of 1024 threads per compute unit, each call 1024 candidates
+ * against 1024 staged words with int8 v_mfma_i32_32x32x32_i8 products and the
+ * max-fold, nothing killed) for `iters` calls and returns the distance checks
+ * per second.  gc_probe_barrier times `iters` team-wide barriers of the
+ * persistent kernel (one team spanning the GPU) and returns microseconds per
+ * barrier.  All run on the null stream and synchronize. */
 int gc_probe_block_loop(int wgs_per_cu, int iters, double *checks_per_s);
+int gc_probe_matrix_loop(int iters, double *checks_per_s);
 int gc_probe_barrier(int iters, double *us_per_barrier);
 
 /* Message of the last failed call on this thread ("" if none). */

@@ -10,7 +10,8 @@ from ._native import (EXPORTS, GC_BORDER, GC_EBUSY, GC_ECAPACITY, GC_EDEVICE, GC
                       greedy_code_batch, greedy_code_capacity, greedy_code_device,
                       greedy_code_device_ex, greedy_code_device_noalloc, greedy_code_tune, greedy_code_tune_reset, load,
                       GcProblem, problem, problem_positions, problem_capacity, greedy_code_problem,
-                      greedy_code_problem_device, device_problem_code, probe_block_loop, probe_barrier)
+                      greedy_code_problem_device, device_problem_code, probe_block_loop, probe_matrix_loop,
+                      probe_barrier)
 
 __all__ = ["EXPORTS", "GC_BORDER", "GC_EBUSY", "GC_ECAPACITY", "GC_EDEVICE", "GC_EINVAL", "GC_ENOMEM",
            "GC_ETIMEOUT", "GC_GRAY", "GC_GREVLEX", "GC_GRLEX", "GC_JOB_ADMITTED", "GC_JOB_DONE",
@@ -19,4 +20,5 @@ __all__ = ["EXPORTS", "GC_BORDER", "GC_EBUSY", "GC_ECAPACITY", "GC_EDEVICE", "GC
            "greedy_code_batch", "greedy_code_capacity", "greedy_code_device",
            "greedy_code_device_ex", "greedy_code_device_noalloc", "greedy_code_tune", "greedy_code_tune_reset", "load",
            "GcProblem", "problem", "problem_positions", "problem_capacity", "greedy_code_problem",
-           "greedy_code_problem_device", "device_problem_code", "probe_block_loop", "probe_barrier"]
+           "greedy_code_problem_device", "device_problem_code", "probe_block_loop", "probe_matrix_loop",
+           "probe_barrier"]

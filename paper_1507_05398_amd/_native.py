@@ -24,7 +24,7 @@ EXPORTS = ["greedy_code_capacity", "greedy_code", "greedy_code_device", "greedy_
            "gc_problem_capacity", "greedy_code_problem", "greedy_code_problem_device",
            "greedy_code_batch", "greedy_code_tune", "greedy_code_tune_reset",
            "greedy_code_batch_tune", "gc_batch_graph_create", "gc_batch_graph_launch",
-           "gc_batch_graph_results", "gc_batch_graph_destroy", "gc_probe_block_loop", "gc_probe_barrier",
+           "gc_batch_graph_results", "gc_batch_graph_destroy", "gc_probe_block_loop", "gc_probe_matrix_loop", "gc_probe_barrier",
            "gc_server_create", "gc_server_submit", "gc_server_poll",
            "gc_server_words", "gc_server_fetch", "gc_server_stats", "gc_server_release",
            "gc_server_drain", "gc_server_destroy", "gc_last_error", "gc_version"]
@@ -148,6 +148,8 @@ def load():
     lib.gc_server_destroy.restype = ctypes.c_int
     lib.gc_probe_block_loop.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     lib.gc_probe_block_loop.restype = ctypes.c_int
+    lib.gc_probe_matrix_loop.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.gc_probe_matrix_loop.restype = ctypes.c_int
     lib.gc_probe_barrier.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     lib.gc_probe_barrier.restype = ctypes.c_int
     lib.gc_last_error.argtypes = []
@@ -361,6 +363,13 @@ def probe_block_loop(wgs_per_cu: int = 1, iters: int = 4096) -> float:
     """Distance checks per second of the screen's block loop alone."""
     v = ctypes.c_double()
     _check(load().gc_probe_block_loop(wgs_per_cu, iters, ctypes.byref(v)))
+    return v.value
+
+
+def probe_matrix_loop(iters: int = 2048) -> float:
+    """Distance checks per second of the matrix-core screen's segment loop alone."""
+    v = ctypes.c_double()
+    _check(load().gc_probe_matrix_loop(iters, ctypes.byref(v)))
     return v.value
 
 

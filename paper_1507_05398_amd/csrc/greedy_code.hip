@@ -1545,6 +1545,30 @@ __global__ void __launch_bounds__(kBlock) probe_block_loop_kernel(int iters, uns
   if (tid == 0) atomicAdd(sink, T.killw[0] + 1ull);
 }
 
+// The matrix screen's segment loop alone: every call screens 1024 live
+// candidates against a staged segment of 1024 words (1,048,576 checks per
+// workgroup) with the threshold above any dot product, so nothing is killed.
+__global__ void __launch_bounds__(kBlock) probe_matrix_loop_kernel(int iters, unsigned long long *sink) {
+  __shared__ TileLds T;
+  __shared__ uint2 lut8[256];
+  const int tid = threadIdx.x;
+  uint32_t h = 2654435761u * (uint32_t)(blockIdx.x * kBlock + tid + 1);
+  for (int i = tid; i < 2 * kSegMax; i += kBlock) {
+    h ^= h << 13; h ^= h >> 17; h ^= h << 5;
+    (&T.seg[0][0])[i] = h;
+  }
+  for (int i = tid; i < 2 * kTile * 8; i += kBlock) {
+    h ^= h << 13; h ^= h >> 17; h ^= h << 5;
+    (&T.cx[0][0][0])[i] = h & 0x01010101u;
+  }
+  if (tid < 256) lut8[tid] = make_uint2(signed_bytes((uint32_t)tid & 15u), signed_bytes((uint32_t)tid >> 4));
+  if (tid < kRows) T.killw[tid] = 0;
+  __syncthreads();
+  for (int it = 0; it < iters; ++it) mfma_segment(T, lut8, 0, it & 1, (unsigned int)kTile, 1024u, 127);
+  __syncthreads();
+  if (tid == 0) atomicAdd(sink, T.killw[0] + 1ull);
+}
+
 // Team barriers alone: the grid joins one team and crosses `iters` barriers.
 __global__ void __launch_bounds__(kBlock) probe_barrier_kernel(Params P, int iters) {
   __shared__ Lds L;
@@ -2202,6 +2226,39 @@ int gc_probe_block_loop(int wgs_per_cu, int iters, double *checks_per_s) {
   release_workspace(slot);
   if (e != hipSuccess) return fail(GC_EDEVICE, "block-loop probe failed: %s", hipGetErrorString(e));
   const double checks = (double)grid * kWaves * (double)iters * 16384.0;
+  *checks_per_s = checks / (ms * 1e-3);
+  return GC_OK;
+}
+
+int gc_probe_matrix_loop(int iters, double *checks_per_s) {
+  g_error.clear();
+  if (!checks_per_s || iters < 1) return fail(GC_EINVAL, "iters >= 1 and checks_per_s non-NULL");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  int cus = 0;
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  char *ws = nullptr;
+  int slot = -1;
+  int rc = acquire_workspace(256, &ws, &slot);
+  if (rc) return rc;
+  unsigned long long *sink = reinterpret_cast<unsigned long long *>(ws);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const unsigned int grid = (unsigned int)cus;
+  if (e == hipSuccess) hipLaunchKernelGGL(probe_matrix_loop_kernel, dim3(grid), dim3(kBlock), 0, nullptr, 4, sink);
+  if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+  if (e == hipSuccess) hipLaunchKernelGGL(probe_matrix_loop_kernel, dim3(grid), dim3(kBlock), 0, nullptr, iters, sink);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  release_workspace(slot);
+  if (e != hipSuccess) return fail(GC_EDEVICE, "matrix-loop probe failed: %s", hipGetErrorString(e));
+  const double checks = (double)grid * (double)iters * 1048576.0;
   *checks_per_s = checks / (ms * 1e-3);
   return GC_OK;
 }
