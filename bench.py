@@ -506,7 +506,11 @@ def main():
         gc.load()
         out = {"peak_gchecks_per_s": round(PEAK_GCHECKS, 1)}
         for k in (1, 2):
-            v = gc.probe_block_loop(wgs_per_cu=k, iters=4096) / 1e9
+            try:
+                v = gc.probe_block_loop(wgs_per_cu=k, iters=4096) / 1e9
+            except gc.GreedyCodeError as e:  # two screen workgroups no longer fit a CU's LDS
+                out[f"block_loop_{k}wg_per_cu"] = str(e)
+                continue
             out[f"block_loop_{k}wg_per_cu_gchecks_per_s"] = round(v, 1)
             out[f"block_loop_{k}wg_per_cu_frac_of_peak"] = round(v / PEAK_GCHECKS, 4)
         v = gc.probe_matrix_loop(iters=2048) / 1e9

@@ -160,7 +160,7 @@ struct TileLds {
   alignas(16) uint32_t cx[2][kTile][8];  // matrix screens: candidate bits as 32 signed bytes, by cw order
   unsigned long long killw[kRows];     // kill mask of each row of 64 live candidates
   unsigned int wcnt[kWaves];
-  unsigned long long claim[2];         // offsets (from the newest end) of claimed segments, by parity
+  unsigned long long claim[2];         // [1]: offset (from the newest end) of the next claimed segment
   uint32_t dloc[32];                   // kills found by this workgroup (the tile's dead-bit words)
   uint32_t dseen[32];                  // the tile's published dead bits, as last loaded
 };
@@ -684,9 +684,11 @@ __device__ __forceinline__ unsigned int seg_len_for(unsigned int live, unsigned 
 
 // Screen candidates id0 .. id0+nc-1 of `src` (nc <= kTile, id0 a multiple of
 // kTile) against code[a, b) with the whole workgroup, one of `members`
-// workgroups that share this tile.  The members share `cursor`: each claims
-// the next segment of the range, newest first (the cursor counts words from
-// b), so together they sweep the range from the newest end.  A segment is at
+// workgroups that share this tile (this one is number `member`).  Member k
+// first screens the k-th newest segment of the tile's first-segment length;
+// then the members share `cursor`: each claims the next segment of the rest
+// of the range, newest first (offsets count words from b), so together they
+// sweep the range from the newest end.  A segment is at
 // most 1/(2 members) of the range (so the last claims do not leave a few
 // members with long tails) and otherwise 64..4096 words, longer as fewer
 // candidates stay live (`blocks`, or `far_blocks` once the sweep is kFarAt
@@ -707,7 +709,7 @@ template <bool SO>
 __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &src, const uint32_t *code, uint32_t id0,
                                           uint32_t nc, unsigned long long a, unsigned long long b,
                                           uint32_t d, unsigned long long *cursor, unsigned int members,
-                                          unsigned int blocks, unsigned int far_blocks = 0) {
+                                          unsigned int member, unsigned int blocks, unsigned int far_blocks = 0) {
   TileLds &T = L.u.t;
   const int tid = threadIdx.x, wave = tid >> 6;
   const unsigned long long len = b > a ? b - a : 0;
@@ -716,16 +718,45 @@ __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &
   const int dwords = (int)((nc + 31) / 32);
   const unsigned long long share = (len / (2ull * members) + 63) & ~63ull;
   const unsigned int cap = share < 64 ? 64u : (share > (unsigned long long)kSegMax ? (unsigned)kSegMax : (unsigned)share);
-  auto claim = [&](unsigned int l) {
-    return __hip_atomic_fetch_add(as_global(cursor), (unsigned long long)l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  };
-  // First claim: a short segment, so that the tile's first sweep is narrow.
-  // It is in flight while the candidates are listed (all of them are live:
-  // the tile's dead bits are clear when a screen starts).
-  unsigned int live = nc;
+  // First segments: short, so that the tile's first sweep is narrow, and
+  // fixed: member k screens the k-th newest (members share one length), so
+  // no claim round trip delays the start.  The cursor hands out the rest of
+  // the range after them.
+  unsigned int live = nc;  // all candidates are live: the tile's dead bits are clear when a screen starts
   unsigned int slen = umin(seg_len_for(live, 16), cap);
-  unsigned long long first = 0;
-  if (tid == 0) first = claim(slen);
+  const unsigned long long off0 = (unsigned long long)member * slen, base = (unsigned long long)members * slen;
+  if (off0 >= len) return 0;
+  auto claim = [&](unsigned int l) {
+    return base + __hip_atomic_fetch_add(as_global(cursor), (unsigned long long)l, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+  };
+  int cur = 0, buf = 0;
+  unsigned long long checks = 0;
+  // The segment goes from global memory straight into LDS buffer `to` (the
+  // loads write LDS themselves; no registers hold the words).  A clipped
+  // segment repeats its oldest word.  The words are in LDS once the issuing
+  // wave's vector-memory counter drains: every wave waits for that before the
+  // barrier after which the buffer is read.
+  auto fetch = [&](unsigned long long o, unsigned int l, int to) {
+    const unsigned long long hi = b - o, lo_s = hi > a + l ? hi - l : a;
+#pragma unroll
+    for (int q = 0; q < kSegLoads; ++q) {
+      const unsigned long long idx = lo_s + tid + (unsigned long long)q * kBlock;
+      if ((unsigned int)(tid + q * kBlock) < l)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(code + (idx < hi ? idx : hi - 1)),
+                                         (__attribute__((address_space(3))) void *)&T.seg[to][q * kBlock + 64 * wave],
+                                         4, 0, 0);
+    }
+  };
+  auto fetched = [] { __builtin_amdgcn_s_waitcnt(0x0f70); };  // vmcnt(0)
+  // Segment blocks at claim offset o (words below the newest end).
+  auto blocks_at = [&](unsigned long long o) { return far_blocks && o >= kFarAt ? far_blocks : blocks; };
+
+  // The first segment and the claim of the second are in flight while the
+  // candidates are listed.
+  fetch(off0, slen, buf);
+  unsigned int next_len = umin(seg_len_for(live, blocks_at(off0)), cap);
+  if (tid == 0) T.claim[1] = claim(next_len);
   bool keep = false;
   uint32_t word = 0, id = 0;
   const bool mx = !SO && L.mfma;
@@ -748,37 +779,8 @@ __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &
     }
   }
   const int thr = L.n - 2 * (int)d;  // matrix screens: a dot product above this is a clash
-  int cur = 0, buf = 0;
-  unsigned long long checks = 0;
-  // The segment goes from global memory straight into LDS buffer `to` (the
-  // loads write LDS themselves; no registers hold the words).  A clipped
-  // segment repeats its oldest word.  The words are in LDS once the issuing
-  // wave's vector-memory counter drains: every wave waits for that before the
-  // barrier after which the buffer is read.
-  auto fetch = [&](unsigned long long o, unsigned int l, int to) {
-    const unsigned long long hi = b - o, lo_s = hi > a + l ? hi - l : a;
-#pragma unroll
-    for (int q = 0; q < kSegLoads; ++q) {
-      const unsigned long long idx = lo_s + tid + (unsigned long long)q * kBlock;
-      if ((unsigned int)(tid + q * kBlock) < l)
-        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(code + (idx < hi ? idx : hi - 1)),
-                                         (__attribute__((address_space(3))) void *)&T.seg[to][q * kBlock + 64 * wave],
-                                         4, 0, 0);
-    }
-  };
-  auto fetched = [] { __builtin_amdgcn_s_waitcnt(0x0f70); };  // vmcnt(0)
-
-  if (tid == 0) T.claim[0] = first;
   if (tid < 32) T.dloc[tid] = 0;
   if (tid < kRows) T.killw[tid] = 0;
-  __syncthreads();
-  const unsigned long long off0 = T.claim[0];
-  if (off0 >= len) return 0;
-  fetch(off0, slen, buf);
-  // Segment blocks at claim offset o (words below the newest end).
-  auto blocks_at = [&](unsigned long long o) { return far_blocks && o >= kFarAt ? far_blocks : blocks; };
-  unsigned int next_len = umin(seg_len_for(live, blocks_at(off0)), cap);
-  if (tid == 0) T.claim[1] = claim(next_len);
   fetched();
   __syncthreads();
   unsigned long long next_off = T.claim[1];
@@ -875,18 +877,19 @@ __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &
 }
 
 // Tiles of a 2-D screen (candidate tiles x one code range) for a team: with
-// fewer tiles than workgroups, workgroup r joins tile r mod tiles and the
-// workgroups of a tile share its range through the tile's cursor; otherwise
-// each workgroup takes tiles r, r + team_size, ... alone.
+// fewer tiles than workgroups, workgroup r joins tile r mod tiles as its
+// member r / tiles and the workgroups of a tile share its range through the
+// tile's cursor; otherwise each workgroup takes tiles r, r + team_size, ...
+// alone.  f(tile, members, member).
 template <typename F>
 __device__ __forceinline__ void for_my_tiles(const Lds &L, unsigned long long tiles, F &&f) {
   const unsigned long long ts = L.team_size, r = L.team_rank;
   if (tiles == 0) return;
   if (tiles < ts) {
     const unsigned long long t = r % tiles;
-    f(t, (unsigned int)((ts - t + tiles - 1) / tiles));
+    f(t, (unsigned int)((ts - t + tiles - 1) / tiles), (unsigned int)(r / tiles));
   } else {
-    for (unsigned long long t = r; t < tiles; t += ts) f(t, 1u);
+    for (unsigned long long t = r; t < tiles; t += ts) f(t, 1u, 0u);
   }
 }
 
@@ -1076,11 +1079,12 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
     // ---- A: near screen of [p0, pe0) against code[lo, m0) -----------------
     if (m0 > lo) {
       const Source src{&L.tab, L.walk, p0, nullptr, W.win_dead};
-      for_my_tiles(L, (nwin + kTile - 1) / kTile, [&](unsigned long long tile, unsigned int members) {
+      for_my_tiles(L, (nwin + kTile - 1) / kTile, [&](unsigned long long tile, unsigned int members,
+                                                      unsigned int member) {
         const unsigned long long id0 = tile * kTile;
         const uint32_t nc = (uint32_t)(nwin - id0 < (unsigned long long)kTile ? nwin - id0 : kTile);
         const unsigned long long c =
-            tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, lo, m0, d, &W.cur[tile], members,
+            tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, lo, m0, d, &W.cur[tile], members, member,
                             lo == 0 ? kDeepBlocks : kNearBlocks);
         if (tid == 0) L.cnt_near += c;
       });
@@ -1178,11 +1182,12 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
       charge(1);
       const Source src{&L.tab, L.walk, 0, L.s1w, W.deep_fail};
       const unsigned int dtile = L.deep_tile;
-      for_my_tiles(L, (L.s + dtile - 1) / dtile, [&](unsigned long long tile, unsigned int members) {
+      for_my_tiles(L, (L.s + dtile - 1) / dtile, [&](unsigned long long tile, unsigned int members,
+                                                     unsigned int member) {
         const unsigned long long id0 = tile * dtile;
         const uint32_t nc = (uint32_t)(L.s - id0 < (unsigned long long)dtile ? L.s - id0 : dtile);
         const unsigned long long c =
-            tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members,
+            tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members, member,
                         kDeepBlocks, kFarBlocks);
         if (tid == 0) L.cnt_deep += c;
       });
@@ -1224,11 +1229,12 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
         const unsigned long long nd = L.ndeep;
         const Source src{&L.tab, L.walk, 0, W.deep_word, W.deep_fail};
         const unsigned int dtile = L.deep_tile;
-        for_my_tiles(L, (nd + dtile - 1) / dtile, [&](unsigned long long tile, unsigned int members) {
+        for_my_tiles(L, (nd + dtile - 1) / dtile, [&](unsigned long long tile, unsigned int members,
+                                                      unsigned int member) {
           const unsigned long long id0 = tile * dtile;
           const uint32_t nc = (uint32_t)(nd - id0 < (unsigned long long)dtile ? nd - id0 : dtile);
           const unsigned long long c =
-              tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members,
+              tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members, member,
                         kDeepBlocks, kFarBlocks);
           if (tid == 0) L.cnt_deep += c;
         });
