@@ -191,6 +191,7 @@ struct Lds {
   unsigned long long p0, m0, w, pe, lo;
   unsigned int s, s_tot, ndeep, round, tcount, truncated;
   unsigned int gen_seen;               // resolve generation before the barrier that precedes a resolve
+  unsigned long long tk;               // phase clock (team rank 0): end of the last charged phase
   int status, action, abort;
   // team
   unsigned int xcd, xcd_members, team, team_rank, team_size, team_xcds;
@@ -221,6 +222,13 @@ __device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p
 template <typename T>
 __device__ __forceinline__ T gload(const T *p) {
   return *(const __attribute__((address_space(1))) T *)p;
+}
+
+// A value every lane holds alike, moved to scalar registers.
+__device__ __forceinline__ unsigned long long uniform64(unsigned long long x) {
+  const unsigned int lo = __builtin_amdgcn_readfirstlane((unsigned int)x);
+  const unsigned int hi = __builtin_amdgcn_readfirstlane((unsigned int)(x >> 32));
+  return ((unsigned long long)hi << 32) | lo;
 }
 
 __device__ __forceinline__ unsigned long long lanemask_lt() {
@@ -707,11 +715,16 @@ __device__ __forceinline__ unsigned int seg_len_for(unsigned int live, unsigned 
 // through generic pointers (measured 15 % slower).
 template <bool SO>
 __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &src, const uint32_t *code, uint32_t id0,
-                                          uint32_t nc, unsigned long long a, unsigned long long b,
-                                          uint32_t d, unsigned long long *cursor, unsigned int members,
-                                          unsigned int member, unsigned int blocks, unsigned int far_blocks = 0) {
+                                          uint32_t nc_v, unsigned long long a_v, unsigned long long b_v,
+                                          uint32_t d, unsigned long long *cursor, unsigned int members_v,
+                                          unsigned int member_v, unsigned int blocks, unsigned int far_blocks = 0) {
   TileLds &T = L.u.t;
   const int tid = threadIdx.x, wave = tid >> 6;
+  // The tile and its range are the same for every lane: scalar registers.
+  const uint32_t nc = __builtin_amdgcn_readfirstlane(nc_v);
+  const unsigned long long a = uniform64(a_v), b = uniform64(b_v);
+  const unsigned int members = __builtin_amdgcn_readfirstlane(members_v);
+  const unsigned int member = __builtin_amdgcn_readfirstlane(member_v);
   const unsigned long long len = b > a ? b - a : 0;
   if (len == 0 || nc == 0) return 0;
   uint32_t *dead = src.dead + (id0 >> 5);  // the tile's dead-bit words
@@ -882,8 +895,11 @@ __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &
 // tile's cursor; otherwise each workgroup takes tiles r, r + team_size, ...
 // alone.  f(tile, members, member).
 template <typename F>
-__device__ __forceinline__ void for_my_tiles(const Lds &L, unsigned long long tiles, F &&f) {
-  const unsigned long long ts = L.team_size, r = L.team_rank;
+__device__ __forceinline__ void for_my_tiles(const Lds &L, unsigned long long tiles_v, F &&f) {
+  // Uniform values, in scalar registers.
+  const unsigned long long ts = __builtin_amdgcn_readfirstlane(L.team_size);
+  const unsigned long long r = __builtin_amdgcn_readfirstlane(L.team_rank);
+  const unsigned long long tiles = uniform64(tiles_v);
   if (tiles == 0) return;
   if (tiles < ts) {
     const unsigned long long t = r % tiles;
@@ -1045,18 +1061,19 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
   const int tid = threadIdx.x;
   const unsigned int lane = tid & 63;
   const uint32_t d = (uint32_t)L.d;
-  const unsigned long long tw = (unsigned long long)L.team_rank * kWaves + (tid >> 6);
-  const unsigned long long tnw = (unsigned long long)L.team_size * kWaves;
+  const unsigned int tw = L.team_rank * kWaves + (unsigned int)(tid >> 6);
+  const unsigned int tnw = L.team_size * kWaves;
   Ctl *ctl = W.ctl;
   // Phase clock (team rank 0 only): time from the end of one team barrier to
-  // the end of the next is charged to the phase in between.
+  // the end of the next is charged to the phase in between.  The clock lives
+  // in LDS: state held in registers across the window loop gets spilled.
   const bool timer = L.team_rank == 0 && tid == 0;
-  unsigned long long tk = timer ? wall_clock64() : 0;
+  if (timer) L.tk = wall_clock64();
   auto charge = [&](int phase) {
     if (timer) {
       const unsigned long long now = wall_clock64();
-      ctl->ticks[phase] += now - tk;
-      tk = now;
+      ctl->ticks[phase] += now - L.tk;
+      L.tk = now;
     }
   };
 
@@ -1070,8 +1087,9 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
     }
     __syncthreads();
     if (L.status != 0 || L.abort || L.p0 >= L.total) break;
-    const unsigned long long p0 = L.p0, m0 = L.m0;
-    const unsigned long long pe0 = p0 + L.w < L.total ? p0 + L.w : L.total;
+    // Window bounds: uniform, held in scalar registers.
+    const unsigned long long p0 = uniform64(L.p0), m0 = uniform64(L.m0);
+    const unsigned long long pe0 = p0 + L.w < L.total ? p0 + L.w : uniform64(L.total);
     const unsigned long long nwin = pe0 - p0;
     const unsigned long long lo = m0 > L.near_depth ? m0 - L.near_depth : 0;
     if (tid == 0) L.lo = lo;
