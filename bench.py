@@ -110,7 +110,7 @@ def digest_of(t):
 def measured_traffic():
     """HBM bytes per greedy_code_kernel launch from the committed counter
     summary, or None when the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "greedy_code_kernel_screens24_28_batched_traffic.md")
+    path = os.path.join(ROOT, "profiles", "greedy_code_kernel_screens24_28_traffic.md")
     if not os.path.exists(path):
         return None
     fields = {}
