@@ -101,8 +101,8 @@ enum : int { MODE_AUTO = 0, MODE_TENTATIVE = 1, MODE_DEEP_ALL = 2 };
 // Per-team workspace, carved out of one buffer.
 struct TeamWs {
   Ctl *ctl;
-  unsigned long long *cur;   // kCursors range cursors: near-screen tiles, then deep tiles
-  uint32_t *win_dead;        // kWMax / 32
+  unsigned long long *cur;   // kCursors range cursors (kCurLate, kCurEarly, kCurDeep)
+  uint32_t *win_dead[2];     // kWMax / 32 each, by window parity
   unsigned long long *adj;   // kAdjWords
   uint32_t *deep_word;       // kSMax
   uint32_t *deep_idx;        // kSMax
@@ -113,11 +113,17 @@ constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 constexpr int kNearTiles = (int)(kWMax / kTile);       // tiles of a window
 constexpr int kMinTile = 256;                          // smallest deep-scan tile (tuning)
 constexpr int kDeepTiles = (kSMax + kMinTile - 1) / kMinTile;  // tiles of a deep list, at most
-constexpr int kCursors = kNearTiles + kDeepTiles;
+// Cursors: the near screen's late part (one per tile), its early part (one
+// per tile and window parity), the deep scan's tiles.
+constexpr int kCurLate = 0;
+constexpr int kCurEarly = kNearTiles;
+constexpr int kCurDeep = 3 * kNearTiles;
+constexpr int kCursors = kCurDeep + kDeepTiles;
 constexpr size_t kOffCtl = 0;
 constexpr size_t kOffCur = align256(sizeof(Ctl));
 constexpr size_t kOffDead = kOffCur + align256(kCursors * sizeof(unsigned long long));
-constexpr size_t kOffAdj = kOffDead + align256(kWMax / 32 * sizeof(uint32_t));
+constexpr size_t kDeadBytes = align256(kWMax / 32 * sizeof(uint32_t));
+constexpr size_t kOffAdj = kOffDead + 2 * kDeadBytes;
 constexpr size_t kOffDword = kOffAdj + align256(kAdjWords * sizeof(unsigned long long));
 constexpr size_t kOffDidx = kOffDword + align256(kSMax * sizeof(uint32_t));
 constexpr size_t kOffDfail = kOffDidx + align256(kSMax * sizeof(uint32_t));
@@ -127,7 +133,8 @@ __host__ __device__ inline TeamWs team_ws(char *base) {
   TeamWs w;
   w.ctl = reinterpret_cast<Ctl *>(base + kOffCtl);
   w.cur = reinterpret_cast<unsigned long long *>(base + kOffCur);
-  w.win_dead = reinterpret_cast<uint32_t *>(base + kOffDead);
+  w.win_dead[0] = reinterpret_cast<uint32_t *>(base + kOffDead);
+  w.win_dead[1] = reinterpret_cast<uint32_t *>(base + kOffDead + kDeadBytes);
   w.adj = reinterpret_cast<unsigned long long *>(base + kOffAdj);
   w.deep_word = reinterpret_cast<uint32_t *>(base + kOffDword);
   w.deep_idx = reinterpret_cast<uint32_t *>(base + kOffDidx);
@@ -192,6 +199,10 @@ struct Lds {
   unsigned int s, s_tot, ndeep, round, tcount, truncated;
   unsigned int gen_seen;               // resolve generation before the barrier that precedes a resolve
   unsigned long long tk;               // phase clock (team rank 0): end of the last charged phase
+  unsigned long long wfull;            // this window's positions before the cut at kSMax survivors
+  unsigned long long e_p0, e_w, e_lo, e_m0;  // the early near screen done for this window (if early)
+  unsigned long long nx_p0, nx_w, nx_lo, nx_m0;  // the early near screen of the next window
+  unsigned int par, early, nx_early;   // window parity; 1 when [e_lo, e_m0) was screened early
   int status, action, abort;
   // team
   unsigned int xcd, xcd_members, team, team_rank, team_size, team_xcds;
@@ -895,10 +906,10 @@ __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &
 // tile's cursor; otherwise each workgroup takes tiles r, r + team_size, ...
 // alone.  f(tile, members, member).
 template <typename F>
-__device__ __forceinline__ void for_my_tiles(const Lds &L, unsigned long long tiles_v, F &&f) {
+__device__ __forceinline__ void for_tiles(unsigned int r_v, unsigned int ts_v, unsigned long long tiles_v, F &&f) {
   // Uniform values, in scalar registers.
-  const unsigned long long ts = __builtin_amdgcn_readfirstlane(L.team_size);
-  const unsigned long long r = __builtin_amdgcn_readfirstlane(L.team_rank);
+  const unsigned long long ts = __builtin_amdgcn_readfirstlane(ts_v);
+  const unsigned long long r = __builtin_amdgcn_readfirstlane(r_v);
   const unsigned long long tiles = uniform64(tiles_v);
   if (tiles == 0) return;
   if (tiles < ts) {
@@ -907,6 +918,29 @@ __device__ __forceinline__ void for_my_tiles(const Lds &L, unsigned long long ti
   } else {
     for (unsigned long long t = r; t < tiles; t += ts) f(t, 1u, 0u);
   }
+}
+
+template <typename F>
+__device__ __forceinline__ void for_my_tiles(const Lds &L, unsigned long long tiles, F &&f) {
+  for_tiles(L.team_rank, L.team_size, tiles, f);
+}
+
+// Length of the window after this one: aim for `target` survivors from this
+// window's density (every workgroup computes it alike from its own state).
+__device__ __forceinline__ unsigned long long next_window_len(const Lds &L) {
+  const unsigned long long nwin = L.pe - L.p0;
+  unsigned long long next;
+  if (L.truncated) {
+    next = nwin * 3 / 4;
+  } else if (L.s_tot == 0) {
+    next = 2 * L.w;
+  } else {
+    next = L.w * L.target / L.s_tot;
+    if (next > 2 * L.w) next = 2 * L.w;
+  }
+  if (next < kWMin) next = kWMin;
+  if (next > kWMax) next = kWMax;
+  return (next + 63) & ~63ull;
 }
 
 // ---------------------------------------------------------------------------
@@ -1000,7 +1034,7 @@ __device__ void resolve_window(Lds &L, const TeamWs &W) {
   const unsigned int tcount = L.tcount, ndeep = L.ndeep;
   if (ndeep > 0) {
     for (unsigned int k = tid; k < (ndeep + 31) / 32; k += kBlock) W.deep_fail[k] = 0;
-    if (tid < kDeepTiles) W.cur[kNearTiles + tid] = 0;
+    if (tid < kDeepTiles) W.cur[kCurDeep + tid] = 0;
     if (tid == 0) {
       ctl->ndeep = ndeep;
       ctl->action = ACT_DEEP;
@@ -1016,23 +1050,18 @@ __device__ void resolve_window(Lds &L, const TeamWs &W) {
   const unsigned int nput = tcount < room ? tcount : (unsigned int)room;
   for (unsigned int k = tid; k < nput; k += kBlock) L.code[m0 + k] = R.tlist[k];
 
-  // Next window length: aim for `target` survivors from this window's density.
-  const unsigned long long nwin = L.pe - L.p0;
-  unsigned long long next;
-  if (L.truncated) {
-    next = nwin * 3 / 4;
-  } else if (L.s_tot == 0) {
-    next = 2 * L.w;
-  } else {
-    next = L.w * L.target / L.s_tot;
-    if (next > 2 * L.w) next = 2 * L.w;
+  const unsigned long long next = next_window_len(L);
+  // Leave this window's dead-bit buffer, its early-screen cursors, the late
+  // and deep cursors all clear for their next use (the window after the next
+  // one takes this buffer; the other is being filled meanwhile by the early
+  // screen of the next window).
+  uint32_t *dead = (L.par ? W.win_dead[1] : W.win_dead[0]);
+  for (unsigned long long k = tid; k < (L.wfull + 31) / 32; k += kBlock) dead[k] = 0;
+  if (tid < kNearTiles) {
+    W.cur[kCurLate + tid] = 0;
+    W.cur[kCurEarly + L.par * kNearTiles + tid] = 0;
   }
-  if (next < kWMin) next = kWMin;
-  if (next > kWMax) next = kWMax;
-  next = (next + 63) & ~63ull;
-  for (unsigned long long k = tid; k < (next + 31) / 32; k += kBlock) W.win_dead[k] = 0;
-  if (tid < kNearTiles) W.cur[tid] = 0;
-  if (tid < kDeepTiles) W.cur[kNearTiles + tid] = 0;
+  if (tid < kDeepTiles) W.cur[kCurDeep + tid] = 0;
   if (tid < kSMax / 32) W.deep_fail[tid] = 0;
 
   if (tid == 0) {
@@ -1069,6 +1098,10 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
   // in LDS: state held in registers across the window loop gets spilled.
   const bool timer = L.team_rank == 0 && tid == 0;
   if (timer) L.tk = wall_clock64();
+  if (tid == 0) {
+    L.par = 0;
+    L.early = 0;
+  }
   auto charge = [&](int phase) {
     if (timer) {
       const unsigned long long now = wall_clock64();
@@ -1091,19 +1124,30 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
     const unsigned long long p0 = uniform64(L.p0), m0 = uniform64(L.m0);
     const unsigned long long pe0 = p0 + L.w < L.total ? p0 + L.w : uniform64(L.total);
     const unsigned long long nwin = pe0 - p0;
-    const unsigned long long lo = m0 > L.near_depth ? m0 - L.near_depth : 0;
-    if (tid == 0) L.lo = lo;
+    // The near screen covers code[lo, m0).  When the team screened this
+    // window against code[e_lo, e_m0) while the previous window was being
+    // resolved (early), the rest is the words that resolve accepted,
+    // code[e_m0, m0); otherwise it is the newest near_depth words.
+    const bool early = L.early != 0;
+    if (early && tid == 0 && (L.e_p0 != p0 || L.e_w != nwin)) set_status(ctl, GC_EDEVICE);  // cannot happen
+    const unsigned long long lo = early ? uniform64(L.e_lo) : (m0 > L.near_depth ? m0 - L.near_depth : 0);
+    const unsigned long long mid = early ? uniform64(L.e_m0) : lo;
+    uint32_t *const win_dead = (L.par ? W.win_dead[1] : W.win_dead[0]);
+    if (tid == 0) {
+      L.lo = lo;
+      L.wfull = nwin;
+    }
 
-    // ---- A: near screen of [p0, pe0) against code[lo, m0) -----------------
-    if (m0 > lo) {
-      const Source src{&L.tab, L.walk, p0, nullptr, W.win_dead};
+    // ---- A: near screen of [p0, pe0) against code[mid, m0) -----------------
+    if (m0 > mid) {
+      const Source src{&L.tab, L.walk, p0, nullptr, win_dead};
       for_my_tiles(L, (nwin + kTile - 1) / kTile, [&](unsigned long long tile, unsigned int members,
                                                       unsigned int member) {
         const unsigned long long id0 = tile * kTile;
         const uint32_t nc = (uint32_t)(nwin - id0 < (unsigned long long)kTile ? nwin - id0 : kTile);
         const unsigned long long c =
-            tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, lo, m0, d, &W.cur[tile], members, member,
-                            lo == 0 ? kDeepBlocks : kNearBlocks);
+            tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, mid, m0, d, &W.cur[kCurLate + tile], members,
+                            member, mid == 0 ? kDeepBlocks : kNearBlocks);
         if (tid == 0) L.cnt_near += c;
       });
     }
@@ -1128,7 +1172,7 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
         const unsigned int wi = tid * per + k;
         liveb[k] = 0;
         if (k < (int)per && wi < nwords) {
-          const uint32_t dead = ld_relaxed(&W.win_dead[wi]);
+          const uint32_t dead = ld_relaxed(&win_dead[wi]);
           const unsigned long long rem = nwin - 32ull * wi;
           const uint32_t valid = rem >= 32 ? 0xffffffffu : ((1u << rem) - 1u);
           liveb[k] = ~dead & valid;
@@ -1205,7 +1249,7 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
         const unsigned long long id0 = tile * dtile;
         const uint32_t nc = (uint32_t)(L.s - id0 < (unsigned long long)dtile ? L.s - id0 : dtile);
         const unsigned long long c =
-            tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members, member,
+            tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kCurDeep + tile], members, member,
                         kDeepBlocks, kFarBlocks);
         if (tid == 0) L.cnt_deep += c;
       });
@@ -1213,6 +1257,23 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
     if (tid == 0) L.gen_seen = ld_relaxed(&ctl->resolved);  // cannot move before this barrier
     team_barrier(L, P, P.spin_limit);
     charge(deep_now ? 3 : 1);
+
+    // The next window is known now: it starts at this window's cut and its
+    // length follows from this window's density.  With more than one
+    // workgroup in the team, the others screen it against this window's near
+    // range while team rank 0 resolves (a deep-scan-all window resolves
+    // once); after the resolve only the words it accepts remain to screen.
+    // (Kept in LDS: values held in registers across the rounds get spilled.)
+    if (tid == 0) {
+      const bool en = L.team_size > 1 && L.mode == MODE_DEEP_ALL && L.pe < L.total;
+      const unsigned long long wn = next_window_len(L);
+      L.nx_early = en ? 1u : 0u;
+      L.nx_p0 = L.pe;
+      L.nx_w = en ? (L.pe + wn < L.total ? wn : L.total - L.pe) : 0;
+      L.nx_lo = m0 > L.near_depth ? m0 - L.near_depth : 0;
+      L.nx_m0 = m0;
+    }
+    __syncthreads();
 
     // ---- D / E rounds ------------------------------------------------------
     for (;;) {
@@ -1226,11 +1287,31 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
         __syncthreads();
         if (tid == 0)
           __hip_atomic_fetch_add(&ctl->resolved, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else if (tid == 0) {
-        wait_change(&ctl->resolved, L.gen_seen, P, P.spin_limit);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        __builtin_amdgcn_s_waitcnt(0);
-        L.abort = ld_relaxed(&P.dq->abort);
+      } else {
+        if (L.round == 0 && L.nx_early && L.nx_m0 > L.nx_lo) {
+          // Early near screen of the next window, by team ranks 1.., into
+          // the other dead-bit buffer with its own cursors.
+          const unsigned int pn = L.par ^ 1u;
+          const unsigned long long w_next = uniform64(L.nx_w), lo_next = uniform64(L.nx_lo);
+          const Source src{&L.tab, L.walk, uniform64(L.nx_p0), nullptr, (pn ? W.win_dead[1] : W.win_dead[0])};
+          for_tiles(L.team_rank - 1, L.team_size - 1, (w_next + kTile - 1) / kTile,
+                    [&](unsigned long long tile, unsigned int members, unsigned int member) {
+                      const unsigned long long id0 = tile * kTile;
+                      const uint32_t nc =
+                          (uint32_t)(w_next - id0 < (unsigned long long)kTile ? w_next - id0 : kTile);
+                      const unsigned long long c = tile_screen<SO>(
+                          L, src, L.code, (uint32_t)id0, nc, lo_next, uniform64(L.nx_m0), d,
+                          &W.cur[kCurEarly + pn * kNearTiles + tile], members, member,
+                          lo_next == 0 ? kDeepBlocks : kNearBlocks);
+                      if (tid == 0) L.cnt_near += c;
+                    });
+        }
+        if (tid == 0) {
+          wait_change(&ctl->resolved, L.gen_seen, P, P.spin_limit);
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          __builtin_amdgcn_s_waitcnt(0);
+          L.abort = ld_relaxed(&P.dq->abort);
+        }
       }
       __syncthreads();
       charge(2);
@@ -1252,7 +1333,7 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
           const unsigned long long id0 = tile * dtile;
           const uint32_t nc = (uint32_t)(nd - id0 < (unsigned long long)dtile ? nd - id0 : dtile);
           const unsigned long long c =
-              tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kNearTiles + tile], members, member,
+              tile_screen<SO>(L, src, L.code, (uint32_t)id0, nc, 0, lo, d, &W.cur[kCurDeep + tile], members, member,
                         kDeepBlocks, kFarBlocks);
           if (tid == 0) L.cnt_deep += c;
         });
@@ -1265,6 +1346,14 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
       charge(3);
     }
     if (L.action == ACT_STOP || L.status != 0 || L.abort) break;
+    if (tid == 0) {  // the next window: its early screen and its buffer parity
+      L.early = L.nx_early;
+      L.e_p0 = L.nx_p0;
+      L.e_w = L.nx_w;
+      L.e_lo = L.nx_lo;
+      L.e_m0 = L.nx_m0;
+      L.par ^= 1u;
+    }
   }
 }
 
@@ -1409,8 +1498,10 @@ __device__ __forceinline__ void persistent_body(Lds &L, const Params &P) {
       c->ticks[0] = c->ticks[1] = c->ticks[2] = c->ticks[3] = 0;
     }
     for (unsigned long long k = (unsigned long long)L.team_rank * kBlock + tid; k < kWMax / 32;
-         k += (unsigned long long)L.team_size * kBlock)
-      W.win_dead[k] = 0;
+         k += (unsigned long long)L.team_size * kBlock) {
+      W.win_dead[0][k] = 0;
+      W.win_dead[1][k] = 0;
+    }
     for (unsigned long long k = (unsigned long long)L.team_rank * kBlock + tid; k < kCursors;
          k += (unsigned long long)L.team_size * kBlock)
       W.cur[k] = 0;
