@@ -93,6 +93,9 @@ constexpr unsigned int kDeepBlocks = 64;
 constexpr unsigned int kFarBlocks = 128;
 constexpr unsigned long long kFarAt = 1ull << 19;
 constexpr unsigned int kDefaultSpin = 1u << 25;
+// Near ranges (words) from which the next window's near screen overlaps the
+// resolve (measured on the n=24..28 screens).
+constexpr unsigned long long kEarlyMinRange = 8192;
 
 enum : int { ST_UNKNOWN = 0, ST_PASS = 1, ST_FAIL = 2 };
 enum : int { ACT_NEXT = 0, ACT_DEEP = 1, ACT_STOP = 2 };
@@ -149,6 +152,15 @@ struct Walk {
   int n, ord;
   int so;                              // self-orthogonal: only even-weight vectors are candidates
 };
+
+// The walk is the same for every lane: its fields in scalar registers.
+__device__ __forceinline__ Walk uniform_walk(const Walk &w) {
+  Walk u;
+  u.n = __builtin_amdgcn_readfirstlane(w.n);
+  u.ord = __builtin_amdgcn_readfirstlane(w.ord);
+  u.so = __builtin_amdgcn_readfirstlane(w.so);
+  return u;
+}
 
 struct Tables {
   union {
@@ -411,9 +423,12 @@ __device__ __forceinline__ uint32_t unrank_weight(const Tables &T, unsigned long
 // last one; GRAY takes the even positions (the reflected Gray word at q has
 // the weight parity of q); graded walks allow the even classes.
 __device__ __forceinline__ uint32_t position_word(const Tables &T, const Walk &K, unsigned long long p) {
-  if (K.ord == GC_LEX) return K.so ? (uint32_t)((p << 1) | (__builtin_popcountll(p) & 1)) : (uint32_t)p;
+  // (The shift is a scalar: a per-lane 0/1 would be hoisted out of the
+  // window loop and held in a vector register.)
+  const unsigned int so = (unsigned int)__builtin_amdgcn_readfirstlane(K.so != 0 ? 1 : 0);
+  if (K.ord == GC_LEX) return (uint32_t)((p << so) | (so & (unsigned int)__builtin_popcountll(p)));
   if (K.ord == GC_GRAY) {
-    const unsigned long long q = K.so ? p << 1 : p;
+    const unsigned long long q = p << so;
     return (uint32_t)(q ^ (q >> 1));
   }
   if (K.ord == GC_BORDER)
@@ -725,13 +740,15 @@ __device__ __forceinline__ unsigned int seg_len_for(unsigned int live, unsigned 
 // Always inlined: called as a function, its LDS arrays would be reached
 // through generic pointers (measured 15 % slower).
 template <bool SO>
-__device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &src, const uint32_t *code, uint32_t id0,
+__device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &src, const uint32_t *code_v, uint32_t id0,
                                           uint32_t nc_v, unsigned long long a_v, unsigned long long b_v,
                                           uint32_t d, unsigned long long *cursor, unsigned int members_v,
                                           unsigned int member_v, unsigned int blocks, unsigned int far_blocks = 0) {
   TileLds &T = L.u.t;
   const int tid = threadIdx.x, wave = tid >> 6;
-  // The tile and its range are the same for every lane: scalar registers.
+  // The tile, its range and the code are the same for every lane: scalar
+  // registers.
+  const uint32_t *code = reinterpret_cast<const uint32_t *>(uniform64(reinterpret_cast<unsigned long long>(code_v)));
   const uint32_t nc = __builtin_amdgcn_readfirstlane(nc_v);
   const unsigned long long a = uniform64(a_v), b = uniform64(b_v);
   const unsigned int members = __builtin_amdgcn_readfirstlane(members_v);
@@ -783,7 +800,7 @@ __device__ __forceinline__ unsigned long long tile_screen(Lds &L, const Source &
   if (tid == 0) T.claim[1] = claim(next_len);
   bool keep = false;
   uint32_t word = 0, id = 0;
-  const bool mx = !SO && L.mfma;
+  const bool mx = !SO && __builtin_amdgcn_readfirstlane(L.mfma) != 0;
   if (tid < (int)nc) {
     id = id0 + tid;
     word = src.word(id);
@@ -1128,7 +1145,7 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
     // window against code[e_lo, e_m0) while the previous window was being
     // resolved (early), the rest is the words that resolve accepted,
     // code[e_m0, m0); otherwise it is the newest near_depth words.
-    const bool early = L.early != 0;
+    const bool early = __builtin_amdgcn_readfirstlane(L.early) != 0;
     if (early && tid == 0 && (L.e_p0 != p0 || L.e_w != nwin)) set_status(ctl, GC_EDEVICE);  // cannot happen
     const unsigned long long lo = early ? uniform64(L.e_lo) : (m0 > L.near_depth ? m0 - L.near_depth : 0);
     const unsigned long long mid = early ? uniform64(L.e_m0) : lo;
@@ -1140,7 +1157,7 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
 
     // ---- A: near screen of [p0, pe0) against code[mid, m0) -----------------
     if (m0 > mid) {
-      const Source src{&L.tab, L.walk, p0, nullptr, win_dead};
+      const Source src{&L.tab, uniform_walk(L.walk), p0, nullptr, win_dead};
       for_my_tiles(L, (nwin + kTile - 1) / kTile, [&](unsigned long long tile, unsigned int members,
                                                       unsigned int member) {
         const unsigned long long id0 = tile * kTile;
@@ -1213,7 +1230,7 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
       }
       __syncthreads();
       // Words of the survivors, one per thread (graded orders unrank in O(n)).
-      for (unsigned int k = tid; k < L.s; k += kBlock) L.s1w[k] = position_word(L.tab, L.walk, p0 + L.s1off[k]);
+      for (unsigned int k = tid; k < L.s; k += kBlock) L.s1w[k] = position_word(L.tab, uniform_walk(L.walk), p0 + L.s1off[k]);
       __syncthreads();
 
       const unsigned int s = L.s;
@@ -1239,10 +1256,11 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
     // Deep-scan-all policy: every survivor against code[0, lo) right away,
     // from this workgroup's own copy of the survivor list (no barrier needed:
     // the scan reads only the list and the committed code).
-    const bool deep_now = L.mode == MODE_DEEP_ALL && lo > 0 && L.s > 0;
+    const bool deep_now =
+        __builtin_amdgcn_readfirstlane(L.mode) == MODE_DEEP_ALL && lo > 0 && __builtin_amdgcn_readfirstlane(L.s) > 0;
     if (deep_now) {
       charge(1);
-      const Source src{&L.tab, L.walk, 0, L.s1w, W.deep_fail};
+      const Source src{&L.tab, uniform_walk(L.walk), 0, L.s1w, W.deep_fail};
       const unsigned int dtile = L.deep_tile;
       for_my_tiles(L, (L.s + dtile - 1) / dtile, [&](unsigned long long tile, unsigned int members,
                                                      unsigned int member) {
@@ -1265,8 +1283,16 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
     // once); after the resolve only the words it accepts remain to screen.
     // (Kept in LDS: values held in registers across the rounds get spilled.)
     if (tid == 0) {
-      const bool en = L.team_size > 1 && L.mode == MODE_DEEP_ALL && L.pe < L.total;
+      // Only when the near range is long enough for the overlap to outweigh
+      // the extra screen pass it costs after the resolve, and the next window
+      // has few enough tiles that each gets at least two of the workgroups
+      // (without rank 0, a window of one tile per workgroup would leave one
+      // of them two tiles).
+      const unsigned long long nr = m0 - (m0 > L.near_depth ? m0 - L.near_depth : 0);
       const unsigned long long wn = next_window_len(L);
+      const unsigned long long tiles_next = (wn + kTile - 1) / kTile;
+      const bool en = L.team_size > 1 && L.mode == MODE_DEEP_ALL && L.pe < L.total && nr >= kEarlyMinRange &&
+                      2 * tiles_next <= L.team_size - 1;
       L.nx_early = en ? 1u : 0u;
       L.nx_p0 = L.pe;
       L.nx_w = en ? (L.pe + wn < L.total ? wn : L.total - L.pe) : 0;
@@ -1293,7 +1319,7 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
           // the other dead-bit buffer with its own cursors.
           const unsigned int pn = L.par ^ 1u;
           const unsigned long long w_next = uniform64(L.nx_w), lo_next = uniform64(L.nx_lo);
-          const Source src{&L.tab, L.walk, uniform64(L.nx_p0), nullptr, (pn ? W.win_dead[1] : W.win_dead[0])};
+          const Source src{&L.tab, uniform_walk(L.walk), uniform64(L.nx_p0), nullptr, (pn ? W.win_dead[1] : W.win_dead[0])};
           for_tiles(L.team_rank - 1, L.team_size - 1, (w_next + kTile - 1) / kTile,
                     [&](unsigned long long tile, unsigned int members, unsigned int member) {
                       const unsigned long long id0 = tile * kTile;
@@ -1326,7 +1352,7 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
       // ---- E: deep scan of the listed survivors against code[0, lo) --------
       {
         const unsigned long long nd = L.ndeep;
-        const Source src{&L.tab, L.walk, 0, W.deep_word, W.deep_fail};
+        const Source src{&L.tab, uniform_walk(L.walk), 0, W.deep_word, W.deep_fail};
         const unsigned int dtile = L.deep_tile;
         for_my_tiles(L, (nd + dtile - 1) / dtile, [&](unsigned long long tile, unsigned int members,
                                                       unsigned int member) {
@@ -1365,7 +1391,7 @@ __device__ void emit_ordering(Lds &L, const TeamWs &W) {
   const unsigned long long count = want < avail ? want : avail;
   const unsigned long long stride = (unsigned long long)L.team_size * kBlock;
   for (unsigned long long k = (unsigned long long)L.team_rank * kBlock + threadIdx.x; k < count; k += stride)
-    L.code[m0 + k] = position_word(L.tab, L.walk, L.p_start + k);
+    L.code[m0 + k] = position_word(L.tab, uniform_walk(L.walk), L.p_start + k);
   if (L.team_rank == 0 && threadIdx.x == 0) {
     W.ctl->m = m0 + count;
     if (count < want) set_status(W.ctl, GC_ECAPACITY);
@@ -1420,7 +1446,9 @@ __device__ __forceinline__ void persistent_body(Lds &L, const Params &P) {
   const int tid = threadIdx.x;
   if (tid < 256) L.lut8[tid] = make_uint2(signed_bytes((uint32_t)tid & 15u), signed_bytes((uint32_t)tid >> 4));
   team_join(L, P);
-  char *base = P.team_ws + (unsigned long long)L.team * P.team_ws_stride;
+  // The team's workspace pointers are uniform: computed in scalar registers.
+  const unsigned int team = __builtin_amdgcn_readfirstlane(L.team);
+  char *base = P.team_ws + (unsigned long long)team * P.team_ws_stride;
   const TeamWs W = team_ws(base);
   // The claim wait (server) may last up to idle_limit polls.
   const unsigned int claim_limit = P.idle_limit + P.spin_limit;
