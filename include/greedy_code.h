@@ -205,7 +205,7 @@ int greedy_code_problem_device(const gc_problem *p, uint32_t *d_words, uint64_t 
  * allocate device memory (tight serving loops, harnesses that forbid
  * hipMalloc).  Same arguments, result and errors as greedy_code_device, but
  * the call allocates nothing: its device workspace (barrier block, queue, one
- * job and one team workspace, about 0.9 MiB) is a fixed array that the
+ * job and one team workspace, about 154 KiB) is a fixed array that the
  * library holds on every device it runs on until the process ends, and the
  * job descriptor reaches the device as a kernel argument.  A launch needs a
  * fixed workspace size, checked against the array's (GC_EINVAL if it were
