@@ -546,7 +546,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": "i8",  # the distance checks are int8 products (int32 sums) on the matrix cores
         "data": "synthetic: the full space F_2^n in each ordering (no dataset)",
         "config": {"workload": name, "instances": len(insts), "w_ee_per_step": w_ee,
                    "w_full_per_step": w_full},
