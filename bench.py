@@ -576,6 +576,7 @@ def main():
         "checks_ceiling_fold_gchecks_per_s": round(FOLD_CHECKS_PEAK_G, 1),
         "frac_of_checks_ceiling": round(sweep.gchecks() / min(MFMA_CHECKS_PEAK_G, FOLD_CHECKS_PEAK_G), 5),
         "valu_screen_peak_gchecks_per_s": round(PEAK_GCHECKS, 1),
+        "frac_of_valu_screen_peak": round(sweep.gchecks() / PEAK_GCHECKS, 5),
         "traffic": measured_traffic(),
         "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE, copy-calibrated)",
         "launches": sweep.launches,
