@@ -209,7 +209,7 @@ struct Lds {
   // window
   unsigned long long p0, m0, w, pe, lo;
   unsigned int s, s_tot, ndeep, round, tcount, truncated;
-  unsigned int gen_seen;               // resolve generation before the barrier that precedes a resolve
+  unsigned int gen_seen;               // resolves of this team seen so far (generation of ctl->resolved)
   unsigned long long tk;               // phase clock (team rank 0): end of the last charged phase
   unsigned long long wfull;            // this window's positions before the cut at kSMax survivors
   unsigned long long e_p0, e_w, e_lo, e_m0;  // the early near screen done for this window (if early)
@@ -218,6 +218,7 @@ struct Lds {
   int status, action, abort;
   // team
   unsigned int xcd, xcd_members, team, team_rank, team_size, team_xcds;
+  unsigned int tgen;                   // team barriers passed (generation of the team's barrier)
   unsigned long long cnt_near, cnt_deep, cnt_pairs;   // this workgroup's executed checks
   unsigned int wsum[kWaves];
   union alignas(16) {
@@ -353,6 +354,10 @@ __device__ __forceinline__ void team_join(Lds &L, const Params &P) {
     L.team_rank = rank;
     L.team_size = ld_relaxed(&B->team[t][2]);
     L.team_xcds = nx;
+    // No team barrier of this launch can complete before every member has
+    // joined, so all members read the same generation here and then count
+    // the barriers they pass.
+    L.tgen = ld_relaxed(&B->team[t][1]);
     L.abort = ld_relaxed(&P.dq->abort);
   }
   __syncthreads();
@@ -363,8 +368,10 @@ __device__ __forceinline__ void team_join(Lds &L, const Params &P) {
 // writes visible device-wide (release) and counts the XCD on the team
 // counter; the last XCD leader bumps the team's generation.  Every workgroup
 // waits for that generation to change and then acquires at agent scope
-// before it reads data written elsewhere.  Waits are bounded by `limit`
-// polls.
+// before it reads data written elsewhere.  The generation a workgroup waits
+// on is its own count of the barriers it has passed (every member passes
+// every barrier, and none completes before all have arrived), so no load
+// precedes the arrival.  Waits are bounded by `limit` polls.
 __device__ __forceinline__ void team_barrier(Lds &L, const Params &P, unsigned int limit) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
@@ -373,8 +380,7 @@ __device__ __forceinline__ void team_barrier(Lds &L, const Params &P, unsigned i
     unsigned int *xc = &B->xcd[L.xcd][0];
     unsigned int *tc = &B->team[L.team][0];
     unsigned int *tgp = &B->team[L.team][1];
-    // The generation cannot move before this workgroup has arrived.
-    const unsigned int tg = ld_relaxed(tgp);
+    const unsigned int tg = L.tgen;
     const unsigned int a = __hip_atomic_fetch_add(xc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (a + 1 == L.xcd_members) {
       __hip_atomic_store(xc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -387,6 +393,7 @@ __device__ __forceinline__ void team_barrier(Lds &L, const Params &P, unsigned i
     wait_change(tgp, tg, P, limit);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __builtin_amdgcn_s_waitcnt(0);
+    L.tgen = tg + 1u;
     L.abort = ld_relaxed(&P.dq->abort);
   }
   __syncthreads();
@@ -1118,6 +1125,10 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
   if (tid == 0) {
     L.par = 0;
     L.early = 0;
+    // The resolve generation is stable here (the last resolve of the team's
+    // previous job is behind a team barrier); from now on every workgroup
+    // counts the resolves it sees.
+    L.gen_seen = ld_relaxed(&ctl->resolved);
   }
   auto charge = [&](int phase) {
     if (timer) {
@@ -1272,7 +1283,6 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
         if (tid == 0) L.cnt_deep += c;
       });
     }
-    if (tid == 0) L.gen_seen = ld_relaxed(&ctl->resolved);  // cannot move before this barrier
     team_barrier(L, P, P.spin_limit);
     charge(deep_now ? 3 : 1);
 
@@ -1339,6 +1349,7 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
           L.abort = ld_relaxed(&P.dq->abort);
         }
       }
+      if (tid == 0) L.gen_seen += 1u;  // this resolve, seen by every workgroup of the team
       __syncthreads();
       charge(2);
       if (tid == 0) {
@@ -1364,10 +1375,7 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
           if (tid == 0) L.cnt_deep += c;
         });
       }
-      if (tid == 0) {
-        L.round += 1;
-        L.gen_seen = ld_relaxed(&ctl->resolved);
-      }
+      if (tid == 0) L.round += 1;
       team_barrier(L, P, P.spin_limit);
       charge(3);
     }
