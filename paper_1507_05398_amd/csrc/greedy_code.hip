@@ -371,7 +371,10 @@ __device__ __forceinline__ void team_join(Lds &L, const Params &P) {
 // before it reads data written elsewhere.  The generation a workgroup waits
 // on is its own count of the barriers it has passed (every member passes
 // every barrier, and none completes before all have arrived), so no load
-// precedes the arrival.  Waits are bounded by `limit` polls.
+// precedes the arrival.  The kernel-wide abort flag is read on arrival, so
+// its round trip overlaps the wait (an abort raised meanwhile is seen at the
+// next wait, where the workgroups still running time out anyway); a wait
+// that expires aborts by itself.  Waits are bounded by `limit` polls.
 __device__ __forceinline__ void team_barrier(Lds &L, const Params &P, unsigned int limit) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
@@ -381,6 +384,7 @@ __device__ __forceinline__ void team_barrier(Lds &L, const Params &P, unsigned i
     unsigned int *tc = &B->team[L.team][0];
     unsigned int *tgp = &B->team[L.team][1];
     const unsigned int tg = L.tgen;
+    const int aborted = ld_relaxed(&P.dq->abort);
     const unsigned int a = __hip_atomic_fetch_add(xc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (a + 1 == L.xcd_members) {
       __hip_atomic_store(xc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -390,11 +394,11 @@ __device__ __forceinline__ void team_barrier(Lds &L, const Params &P, unsigned i
         __hip_atomic_fetch_add(tgp, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
-    wait_change(tgp, tg, P, limit);
+    const bool passed = wait_change(tgp, tg, P, limit);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __builtin_amdgcn_s_waitcnt(0);
     L.tgen = tg + 1u;
-    L.abort = ld_relaxed(&P.dq->abort);
+    L.abort = aborted != 0 || !passed;
   }
   __syncthreads();
 }
@@ -1342,11 +1346,12 @@ __device__ __forceinline__ void build_code(Lds &L, const Params &P, const TeamWs
                       if (tid == 0) L.cnt_near += c;
                     });
         }
-        if (tid == 0) {
-          wait_change(&ctl->resolved, L.gen_seen, P, P.spin_limit);
+        if (tid == 0) {  // the abort flag read before the wait, as at a team barrier
+          const int aborted = ld_relaxed(&P.dq->abort);
+          const bool passed = wait_change(&ctl->resolved, L.gen_seen, P, P.spin_limit);
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           __builtin_amdgcn_s_waitcnt(0);
-          L.abort = ld_relaxed(&P.dq->abort);
+          L.abort = aborted != 0 || !passed;
         }
       }
       if (tid == 0) L.gen_seen += 1u;  // this resolve, seen by every workgroup of the team
