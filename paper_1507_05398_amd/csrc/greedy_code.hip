@@ -1666,7 +1666,7 @@ __global__ void init_job_kernel(Bar *bar, DevQueue *dq, Job *dst, Job job) {
 }
 
 // Workspace of greedy_code_device_noalloc: barrier block, queue, one job and
-// one team workspace (about 0.9 MiB), held by every device the library runs
+// one team workspace (about 154 KiB), held by every device the library runs
 // on until the process ends.  Host code reaches it only through the address
 // hipGetSymbolAddress returns for the current device.
 constexpr size_t kScratchBytes =
