@@ -116,7 +116,7 @@ int greedy_code(int n, int d, int ordering, uint32_t *out_words, uint64_t *out_c
  * `capacity` uint32, caller-owned, e.g. a torch tensor's data_ptr), the count
  * to *d_count (one device uint64), both written on `hip_stream` (a
  * hipStream_t, NULL = null stream).  The call uses a device workspace of
- * about 1 MiB from a pool the library keeps per device (allocated with
+ * about 154 KiB from a pool the library keeps per device (allocated with
  * hipMalloc the first time a call needs one, reused by later calls, held
  * until the process ends; concurrent calls get distinct workspaces).
  * GC_ECAPACITY: the first `capacity` words and *d_count = capacity. */
