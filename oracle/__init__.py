@@ -23,6 +23,10 @@ Functions follow Paliwal et al., arXiv:1507.05398:
     optional self-orthogonality constraint of section "Self Orthogonal Greedy
     Codes Implementation".
   * ``verify_certificate_list`` -- the certificate for a candidate list.
+  * ``weight_class64``, ``greedy_list64``, ``verify_certificate64`` -- the
+    same for uint64 words of length n <= 64 (section "Some Examples" reports
+    constant-weight codes up to length 35): weight classes listed subset by
+    subset in increasing value, never through the 2^n walk.
   * ``distance`` -- Hamming distance, section "Hamming Distance".
 
 Parity: the GREVLEX tie-break is "parity unpinned" beyond the textbook
@@ -82,12 +86,26 @@ def _load():
     lib.gco_verify_certificate_list.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, u32p,
                                                 ctypes.c_uint64, u32p, ctypes.c_uint64]
     lib.gco_verify_certificate_list.restype = ctypes.c_int
+    lib.gco_distance64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    lib.gco_distance64.restype = ctypes.c_uint
+    lib.gco_weight_class64.argtypes = [ctypes.c_int, ctypes.c_int, u64p, ctypes.c_uint64, u64p]
+    lib.gco_weight_class64.restype = ctypes.c_int
+    lib.gco_greedy_list64.argtypes = [ctypes.c_int, ctypes.c_int, u64p, ctypes.c_uint64, u64p, ctypes.c_uint64,
+                                      u64p, u64p, u64p]
+    lib.gco_greedy_list64.restype = ctypes.c_int
+    lib.gco_verify_certificate64.argtypes = [ctypes.c_int, ctypes.c_int, u64p, ctypes.c_uint64, u64p,
+                                             ctypes.c_uint64]
+    lib.gco_verify_certificate64.restype = ctypes.c_int
     _lib = lib
     return lib
 
 
 def _u32(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+def _u64(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
 
 
 class OracleError(RuntimeError):
@@ -213,3 +231,42 @@ def verify_certificate_list(n: int, d: int, candidates, words, self_orth: bool =
     wp = _u32(w) if w.size else None
     return int(_load().gco_verify_certificate_list(n, d, int(bool(self_orth)), _u32(cand), cand.size,
                                                    wp, w.size))
+
+
+def distance64(a: int, b: int) -> int:
+    """Hamming distance of two words of up to 64 coordinates."""
+    return int(_load().gco_distance64(a, b))
+
+
+def weight_class64(n: int, w: int) -> np.ndarray:
+    """The weight-w vectors of length n <= 64 in increasing value (uint64)."""
+    cap = max(1, math.comb(n, w)) if 0 <= w <= n else 1
+    out = np.zeros(cap, dtype=np.uint64)
+    ln = ctypes.c_uint64()
+    rc = _load().gco_weight_class64(n, w, _u64(out), cap, ctypes.byref(ln))
+    if rc:
+        raise OracleError(rc, "weight_class64")
+    return out[: ln.value].copy()
+
+
+def greedy_list64(n: int, d: int, candidates, cap: int = None):
+    """Plain-scan greedy over a list of uint64 candidates (n <= 64).  Returns
+    (words, w_ee, w_full)."""
+    cand = np.ascontiguousarray(candidates, dtype=np.uint64)
+    cap = max(cand.size, 1) if cap is None else cap
+    out = np.zeros(max(cap, 1), dtype=np.uint64)
+    count, ee, full = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    rc = _load().gco_greedy_list64(n, d, _u64(cand) if cand.size else None, cand.size, _u64(out), cap,
+                                   ctypes.byref(count), ctypes.byref(ee), ctypes.byref(full))
+    if rc:
+        raise OracleError(rc, "greedy_list64")
+    return out[: count.value].copy(), ee.value, full.value
+
+
+def verify_certificate64(n: int, d: int, candidates, words) -> int:
+    """0 if ``words`` is the greedy output over ``candidates`` (uint64, n <=
+    64); else 1/2/3 = order / clash / maximality rule failed."""
+    cand = np.ascontiguousarray(candidates, dtype=np.uint64)
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    return int(_load().gco_verify_certificate64(n, d, _u64(cand) if cand.size else None, cand.size,
+                                                _u64(w) if w.size else None, w.size))
