@@ -201,6 +201,22 @@ int greedy_code_problem_device(const gc_problem *p, uint32_t *d_words, uint64_t 
                                uint64_t *d_count, void *hip_stream, const gc_tuning *tuning,
                                gc_stats *stats);
 
+/* Constant-weight greedy code over words of up to 64 coordinates (section
+ * "Brief overview of the Greedy Algorithm and Codes": the candidates are the
+ * weight-w vectors; section "Some Examples" reports such codes up to length
+ * 35, past 32-bit words).  Candidates are the weight-w vectors of length n in
+ * increasing value (as integers); a candidate is appended when its Hamming
+ * distance to every word already in the code is at least d.  n in 1..64,
+ * w in 0..n, d >= 1, at most 2^32 candidates (C(n, w)).  The words go to
+ * d_words (device array of `capacity` uint64, 8-byte aligned, caller-owned),
+ * the count to *d_count (device uint64, may be NULL).  Runs on hip_stream and
+ * returns when the code is complete; uses a small device workspace from the
+ * library's per-device pool.  GC_EINVAL: an argument out of range;
+ * GC_ECAPACITY: the first `capacity` words and *d_count = capacity;
+ * GC_EDEVICE: launch or device failure. */
+int greedy_code_cw64(int n, int w, int d, uint64_t *d_words, uint64_t capacity, uint64_t *d_count,
+                     void *hip_stream);
+
 /* No-allocation variant of greedy_code_device, for callers that cannot
  * allocate device memory (tight serving loops, harnesses that forbid
  * hipMalloc).  Same arguments, result and errors as greedy_code_device, but

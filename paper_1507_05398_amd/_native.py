@@ -20,7 +20,7 @@ GC_JOB_WAITING, GC_JOB_ADMITTED, GC_JOB_DONE, GC_JOB_FAILED = 0, 1, 2, 3
 
 # Every symbol declared in include/greedy_code.h.
 EXPORTS = ["greedy_code_capacity", "greedy_code", "greedy_code_device", "greedy_code_device_ex",
-           "greedy_code_device_noalloc", "gc_problem_init", "gc_problem_positions",
+           "greedy_code_device_noalloc", "greedy_code_cw64", "gc_problem_init", "gc_problem_positions",
            "gc_problem_capacity", "greedy_code_problem", "greedy_code_problem_device",
            "greedy_code_batch", "greedy_code_tune", "greedy_code_tune_reset",
            "greedy_code_batch_tune", "gc_batch_graph_create", "gc_batch_graph_launch",
@@ -95,6 +95,8 @@ def load():
     lib.greedy_code_device_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
                                                ctypes.c_uint64, vp, vp]
     lib.greedy_code_device_noalloc.restype = ctypes.c_int
+    lib.greedy_code_cw64.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_uint64, vp, vp]
+    lib.greedy_code_cw64.restype = ctypes.c_int
     pp = ctypes.POINTER(GcProblem)
     lib.gc_problem_init.argtypes = [pp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.gc_problem_init.restype = ctypes.c_int
@@ -216,6 +218,15 @@ def greedy_code_device_noalloc(n: int, d: int, ordering, words, count, stream=No
     rc = load().greedy_code_device_noalloc(n, d, _ordering(ordering), ctypes.c_void_p(words.data_ptr()),
                                            words.numel(), ctypes.c_void_p(count.data_ptr()),
                                            _stream_ptr(stream))
+    _check(rc)
+
+
+def greedy_code_cw64(n: int, w: int, d: int, words, count, stream=None) -> None:
+    """Constant-weight greedy code over uint64 words (n <= 64): the weight-w
+    vectors in increasing value; ``words`` is a device int64/uint64 tensor of
+    capacity words, ``count`` a device int64 tensor of one element."""
+    rc = load().greedy_code_cw64(n, w, d, ctypes.c_void_p(words.data_ptr()), words.numel(),
+                                 ctypes.c_void_p(count.data_ptr()), _stream_ptr(stream))
     _check(rc)
 
 

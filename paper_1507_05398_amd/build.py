@@ -5,7 +5,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", name) for name in ("greedy_code.hip", "server.hip", "batch_graph.hip")]
+SOURCES = [os.path.join(HERE, "csrc", name) for name in ("greedy_code.hip", "server.hip", "batch_graph.hip", "cw64.hip")]
 HEADERS = [os.path.join(ROOT, "include", "greedy_code.h")]
 LIBRARY = os.path.join(HERE, "libgreedy_code.so")
 ARCH = "gfx950"

@@ -231,3 +231,18 @@ def test_tuning_valu_screen_is_validated():
     rc = lib.greedy_code_device_ex(8, 3, 0, ctypes.c_void_p(64), 16, ctypes.c_void_p(64), None,
                                    ctypes.byref(t), None)
     assert rc == gc.GC_EINVAL and "valu_screen" in gc.gc_last_error()
+
+
+@pytest.mark.parametrize("n,w,d,words,cap", [
+    (0, 1, 2, 64, 16), (65, 1, 2, 64, 16),       # length outside 1..64
+    (35, -1, 2, 64, 16), (35, 36, 2, 64, 16),     # weight outside 0..n
+    (35, 3, 0, 64, 16),                           # d below 1
+    (35, 3, 4, None, 16),                         # no output with room for words
+    (35, 3, 4, 68, 16),                           # output not 8-byte aligned
+    (64, 32, 4, 64, 16), (40, 20, 4, 64, 16),     # more than 2^32 candidates
+])
+def test_cw64_arguments_rejected_before_device(n, w, d, words, cap):
+    lib = gc.load()
+    ptr = None if words is None else ctypes.c_void_p(words)
+    assert lib.greedy_code_cw64(n, w, d, ptr, cap, None, None) == gc.GC_EINVAL
+    assert gc.gc_last_error()
