@@ -246,3 +246,19 @@ def test_cw64_arguments_rejected_before_device(n, w, d, words, cap):
     ptr = None if words is None else ctypes.c_void_p(words)
     assert lib.greedy_code_cw64(n, w, d, ptr, cap, None, None) == gc.GC_EINVAL
     assert gc.gc_last_error()
+
+
+def test_header_is_plain_c(tmp_path):
+    # The boundary is a C ABI: the header compiles as strict C99 (plain
+    # pointers and sizes, no C++ or framework types).
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "use_header.c"
+    src.write_text('#include "greedy_code.h"\nint main(void) { return GC_OK; }\n')
+    include = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    r = subprocess.run([gcc, "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror", "-I", include,
+                        "-c", str(src), "-o", str(tmp_path / "use_header.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
